@@ -1,0 +1,180 @@
+/*
+ * nmfa.h -- C ABI of the MI355X (gfx950) noisy mean-field annealing library (libnmfa.so).
+ *
+ * Noisy mean-field annealing (NMFA) is Algorithm 1 of A. D. King, W. Bernoudy, J. King,
+ * A. J. Berkley, T. Lanting, "Emulating the coherent Ising machine with a mean-field algorithm"
+ * (arXiv:1806.08422, Sec. II). Given an Ising problem (h, J) and parameters T (a decreasing
+ * temperature schedule), sigma and alpha it produces samples s~ in {-1,+1}^N; this library runs
+ * R independent samples ("replicas") at once on one GPU:
+ *
+ *   s_i := 0
+ *   for t = 1..t_f:
+ *     Phi_i := (h_i + sum_j J_ij s_j) / sqrt(h_i^2 + sum_j J_ij^2) + N(0, sigma)   for all i
+ *     s^_i  := -tanh(Phi_i / T_t)                                                 for all i
+ *     s_i   := alpha s^_i + (1 - alpha) s_i                                        for all i
+ *   s~_i := s_i / |s_i|
+ *
+ * and evaluates the Ising energy of Eq. 1, H = sum_{i<j} J_ij s~_i s~_j + sum_i h_i s~_i.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns an int status: NMFA_OK (0) or a negative NMFA_E* code. A failing call
+ *     leaves a message retrievable with nmfa_last_error() (thread-local) and never aborts.
+ *   - Matrices are dense, row-major, with the given leading dimension n. Pointers are HOST
+ *     pointers unless the argument says "device". The caller owns every buffer it passes in;
+ *     the library deep-copies what it keeps.
+ *   - Noise: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed (low word first), with
+ *     counter (floor(i/4), r, t, 0) for spin i of replica r at iteration t (1-based). Its four
+ *     output words give four uniforms and Box-Muller turns (u0,u1), (u2,u3) into the Gaussians
+ *     of spins 4q..4q+3. Replica r's noise does not depend on R, so replica r of any run with
+ *     the same seed, instance and parameters sees the same noise.
+ *   - Temperature schedule (the paper's Fig. 2 is a three-segment piecewise-exponential
+ *     schedule whose values are not printed): knots (u_k, T_k), u_0 = 0 < ... < u_K = 1, log T
+ *     linear between knots, T_t = T((t-1)/(t_f-1)). The default knots are
+ *     (0, 10) (0.1, 2) (0.6, 0.5) (1, 0.05).
+ */
+#ifndef NMFA_H
+#define NMFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------------------------- */
+#define NMFA_OK 0
+#define NMFA_EINVAL (-1)    /* invalid argument (sizes, non-symmetric J, NaN, bad schedule...) */
+#define NMFA_ENOMEM (-2)    /* device or host allocation failed, or a budget is exceeded */
+#define NMFA_EDEVICE (-3)   /* a HIP runtime call failed (message names it) */
+#define NMFA_ESTATE (-4)    /* call out of order, e.g. spins requested before any anneal */
+#define NMFA_ECANCELED (-5) /* serving: the request was cancelled */
+
+/* ---- precisions ------------------------------------------------------------------------------
+ * NMFA_FP64       J, S and all epilogue arithmetic in FP64 (validation path; FP64 MFMA).
+ * NMFA_FP32       J and S in FP32 on FP32 MFMA; normalisation, noise, tanh and state in FP32.
+ * NMFA_BF16       J and S rounded to BF16 on BF16 MFMA with FP32 accumulation; FP32 epilogue and
+ *                 FP32 master state (S is a BF16 copy of the FP32 state).
+ * NMFA_FP8J_BF16S J stored as FP8 E4M3 (exact for integers |J| <= 16), widened to BF16 for the
+ *                 MFMA; spins as in NMFA_BF16.
+ * J values that the chosen storage type cannot represent are rounded to nearest; the energies
+ * are always computed from the exact couplings given to nmfa_create. */
+typedef enum nmfa_precision {
+  NMFA_FP64 = 0,
+  NMFA_FP32 = 1,
+  NMFA_BF16 = 2,
+  NMFA_FP8J_BF16S = 3
+} nmfa_precision;
+
+/* ---- flags ------------------------------------------------------------------------------------ */
+#define NMFA_FLAG_NEGATE_NOISE 0x1u   /* test hook: use -z for every Gaussian z */
+#define NMFA_FLAG_UPPER_TRIANGULAR 0x2u /* J holds only i<j; the library mirrors it */
+#define NMFA_FLAG_FORCE_STEP 0x4u     /* use the per-iteration (large-N) kernel even if N is small */
+
+/* ---- parameters ------------------------------------------------------------------------------
+ * Fill with nmfa_params_default() and override fields. struct_size must be sizeof(nmfa_params)
+ * (ABI versioning). Pointers inside are read during nmfa_create only. */
+typedef struct nmfa_params {
+  uint32_t struct_size;
+  uint32_t precision;      /* nmfa_precision */
+  double alpha;            /* damping, 0 < alpha <= 1; paper: 0.15 (Sec. II) */
+  double sigma;            /* noise standard deviation, >= 0; paper: 0.15 (Sec. II) */
+  int32_t n_knots;         /* 0: default schedule; else number of (knot_u, knot_T) pairs */
+  const double *knot_u;    /* n_knots increasing values, first 0 and last 1 (if n_knots > 1) */
+  const double *knot_T;    /* n_knots temperatures > 0 */
+  uint32_t flags;          /* NMFA_FLAG_* */
+  int32_t record_iters;    /* keep s after each of the first record_iters iterations */
+} nmfa_params;
+
+typedef struct nmfa_ctx nmfa_ctx;
+
+/* Defaults: alpha = sigma = 0.15, default schedule, NMFA_BF16, no flags, no recording. */
+void nmfa_params_default(nmfa_params *p);
+
+/* Create a solver for the instance (h, J) (Eq. 1; Alg. 1 inputs).
+ *   n      number of spins, 1 <= n <= 16384
+ *   J      host, n*n doubles: symmetric with zero diagonal (or the upper triangle with
+ *          NMFA_FLAG_UPPER_TRIANGULAR), finite
+ *   h      host, n doubles, or NULL for h = 0
+ *   p      parameters (NULL: defaults)
+ *   out    receives the handle; release it with nmfa_destroy
+ * Computes the normalisers sqrt(h_i^2 + sum_j J_ij^2) in FP64 (a zero normaliser makes that
+ * spin's field term 0), converts J to the precision's storage type and uploads everything to
+ * the current HIP device. Errors: EINVAL, ENOMEM, EDEVICE. */
+int nmfa_create(int32_t n, const double *J, const double *h, const nmfa_params *p, nmfa_ctx **out);
+
+/* Run the whole anneal: iterations 1..t_f of Algorithm 1 on R replicas, then the sign readout
+ * and the energies of all R samples, enqueued on `hip_stream` (a hipStream_t; NULL = the null
+ * stream). Asynchronous: returns after enqueueing; results are read with nmfa_spins /
+ * nmfa_energies, which synchronise. Device buffers are (re)allocated only when R grows.
+ * Errors: EINVAL (R < 1, t_f < 1), ENOMEM, EDEVICE. */
+int nmfa_anneal(nmfa_ctx *c, int32_t R, int32_t t_f, uint64_t seed, void *hip_stream);
+
+/* Checkpoint/resume form: run iterations t_begin..t_end (1 <= t_begin <= t_end <= t_f) of a
+ * t_f-iteration schedule. t_begin = 1 starts from s = 0; t_begin > 1 continues from the state
+ * the previous call left (same R, t_f, seed) or from nmfa_set_state. The readout and energies
+ * are recomputed after every call. Errors: EINVAL, ESTATE (no state to continue), ENOMEM, EDEVICE. */
+int nmfa_anneal_range(nmfa_ctx *c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end,
+                      uint64_t seed, void *hip_stream);
+
+/* Copy the R*n readout spins s~ (+1/-1, replica-major) to `out` (host, or device if on_device).
+ * Synchronises the anneal's stream. Errors: ESTATE, EDEVICE. */
+int nmfa_spins(nmfa_ctx *c, int8_t *out, int32_t on_device);
+
+/* Copy the R energies H(s~) (Eq. 1 over pairs i<j) to E (host, R doubles). If J and h are
+ * integral, E_int (host, R int64, or NULL) receives the exact integer energies; otherwise
+ * E_int is filled with 0. Synchronises. Errors: ESTATE, EDEVICE. */
+int nmfa_energies(nmfa_ctx *c, double *E, int64_t *E_int);
+
+/* MAX-CUT values (Table I convention, J = edge weights, h = 0): cut_r = (sum_{i<j} J_ij - H_r)/2.
+ * Host, R doubles. Errors: ESTATE, EDEVICE. */
+int nmfa_cuts(nmfa_ctx *c, double *cut);
+
+/* Energies (and exact integer energies if J, h are integral) of R caller-supplied spin vectors
+ * (host, R*n int8 of +1/-1). Synchronous. Errors: EINVAL, ENOMEM, EDEVICE. */
+int nmfa_energies_of(nmfa_ctx *c, int32_t R, const int8_t *spins, double *E, int64_t *E_int);
+
+/* Continuous state s after the last call (host, R*n doubles, widened from FP32 on the FP32/BF16
+ * paths). Synchronises. Errors: ESTATE, EDEVICE. */
+int nmfa_get_state(nmfa_ctx *c, double *out);
+
+/* Replace the continuous state (host, R*n doubles, rounded to the master precision), e.g. to
+ * resume from a checkpoint with nmfa_anneal_range(t_begin > 1). Errors: EINVAL, ENOMEM, EDEVICE. */
+int nmfa_set_state(nmfa_ctx *c, int32_t R, const double *in);
+
+/* Trajectory of the last call: out[(k*R + r)*n + i] = s_i of replica r after its k-th iteration,
+ * k < min(record_iters, iterations run) (host, doubles). Errors: ESTATE, EDEVICE. */
+int nmfa_trajectory(nmfa_ctx *c, double *out);
+
+/* Information about a context: writes n, the precision and the kernel path the last anneal used
+ * (0 = persistent small-N kernel, 1 = per-iteration kernel). Errors: EINVAL. */
+int nmfa_info(nmfa_ctx *c, int32_t *n, int32_t *precision, int32_t *path);
+
+/* Device time of the last anneal in milliseconds, from HIP events recorded on the anneal's own
+ * stream: *anneal_ms covers the annealing kernel launches only (Algorithm 1's iterations),
+ * *total_ms also the readout and the energy evaluation; *launches is the number of annealing
+ * kernel launches (1 for the persistent kernels, one per iteration for the per-iteration path).
+ * Any output pointer may be NULL. Synchronises. Errors: ESTATE, EDEVICE. */
+int nmfa_last_timing(nmfa_ctx *c, double *anneal_ms, double *total_ms, int32_t *launches);
+
+/* Release every device and host resource of the context (NULL is ignored). */
+void nmfa_destroy(nmfa_ctx *c);
+
+/* ---- noise stream utilities (the generator the anneal uses, exposed for reproducibility) ----
+ * nmfa_noise_words: the Philox4x32-10 output words for counters (q, r0+k, t, 0), k < n_rep,
+ *   q < n_quads: out[4*(k*n_quads + q) + w] (host, 4*n_rep*n_quads uint32).
+ * nmfa_noise_values: the corresponding standard normal numbers z(t, r0+k, 4q+w) as the FP64
+ *   path (fp64 = 1) or the FP32 paths (fp64 = 0) compute them, widened to double.
+ * Synchronous. Errors: EINVAL, ENOMEM, EDEVICE. */
+int nmfa_noise_words(uint64_t seed, int32_t t, int32_t r0, int32_t n_rep, int32_t n_quads, uint32_t *out);
+int nmfa_noise_values(uint64_t seed, int32_t t, int32_t r0, int32_t n_rep, int32_t n_quads, int32_t fp64,
+                      double *out);
+
+/* Human-readable message of the last failing call on this thread ("" if none). */
+const char *nmfa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMFA_H */

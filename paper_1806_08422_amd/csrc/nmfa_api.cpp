@@ -1,0 +1,722 @@
+// C-ABI layer of libnmfa.so: argument validation, host-side setup (normalisers, schedule,
+// operand conversion), device buffers and kernel dispatch. Declarations and the contract of
+// every entry point are in include/nmfa.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nmfa.h"
+#include "nmfa_internal.h"
+
+using namespace nmfa;
+
+// ------------------------------------------------------------------------------------------
+// Error reporting
+// ------------------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(_e == hipErrorOutOfMemory ? NMFA_ENOMEM : NMFA_EDEVICE, "%s failed: %s", \
+                  #expr, hipGetErrorString(_e));                                            \
+  } while (0)
+
+extern "C" const char* nmfa_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------------------------------
+// Host helpers
+// ------------------------------------------------------------------------------------------
+static const double kDefaultKnotU[4] = {0.0, 0.1, 0.6, 1.0};
+static const double kDefaultKnotT[4] = {10.0, 2.0, 0.5, 0.05};
+
+static size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
+
+// Temperature of iteration t (1-based) of a t_f-iteration run: log T is linear in relative time
+// between consecutive knots (the paper's three-segment piecewise-exponential schedule, Fig. 2).
+static double schedule_T(const std::vector<double>& ku, const std::vector<double>& kT, int t, int t_f) {
+  const size_t K = kT.size();
+  if (K == 1) return kT[0];
+  const double u = (t_f <= 1) ? 0.0 : double(t - 1) / double(t_f - 1);
+  size_t seg = 0;
+  while (seg + 2 < K && u > ku[seg + 1]) ++seg;
+  if (u == ku[seg]) return kT[seg];
+  if (u == ku[seg + 1]) return kT[seg + 1];
+  const double w = (u - ku[seg]) / (ku[seg + 1] - ku[seg]);
+  return std::exp((1.0 - w) * std::log(kT[seg]) + w * std::log(kT[seg + 1]));
+}
+
+static uint16_t bf16_bits(double v) {
+  float f = (float)v;
+  uint32_t b;
+  std::memcpy(&b, &f, 4);
+  b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest even (finite values)
+  return (uint16_t)(b >> 16);
+}
+
+// FP8 E4M3 ("fn": bias 7, max 448, no infinities), round to nearest even, saturating.
+static uint8_t fp8e4m3_bits(double v) {
+  const uint8_t sign = std::signbit(v) ? 0x80 : 0x00;
+  double a = std::fabs(v);
+  if (a == 0.0) return sign;
+  if (a >= 464.0) return sign | 0x7e;
+  int e2;
+  std::frexp(a, &e2);
+  int ex = e2 - 1;  // a = 2^ex * (1 + f)
+  if (ex < -6) {
+    double k = std::nearbyint(a * 512.0);  // subnormal step 2^-9
+    if (k >= 8.0) return sign | 0x08;      // rounds up to the smallest normal 2^-6
+    return sign | (uint8_t)k;
+  }
+  double f = std::nearbyint((a / std::ldexp(1.0, ex) - 1.0) * 8.0);
+  if (f >= 8.0) {
+    f = 0.0;
+    ex += 1;
+  }
+  if (ex > 8 || (ex == 8 && f > 6.0)) return sign | 0x7e;
+  return sign | (uint8_t)((ex + 7) << 3) | (uint8_t)f;
+}
+
+static bool is_integral(double v) { return std::isfinite(v) && v == std::floor(v) && std::fabs(v) < 9e15; }
+
+// ------------------------------------------------------------------------------------------
+// Context
+// ------------------------------------------------------------------------------------------
+struct nmfa_ctx {
+  int n = 0;
+  int prec = NMFA_BF16;
+  int path = 0;  // 0 = persistent small-N kernel, 1 = per-iteration kernel
+  int Mp = 0, Kp = 0, lds_stride = 0;
+  double alpha = 0.15, sigma = 0.15;
+  uint32_t flags = 0;
+  int record = 0;
+  std::vector<double> ku, kT;
+  std::vector<double> h;  // empty if h = 0
+  bool has_h = false;
+  bool J_integral = false, h_integral = true;
+  double w_total = 0.0;  // sum_{i<j} J_ij
+  int device = 0;
+
+  // device data of the instance
+  void* d_J = nullptr;       // operand layout of the selected path
+  void* d_inv = nullptr;     // [Mp] acc_t
+  void* d_hterm = nullptr;   // [Mp] acc_t
+  int8_t* d_J8 = nullptr;    // [n][n] for exact energies (integral |J| <= 127)
+  double* d_J64 = nullptr;   // [n][n] otherwise
+  double* d_h = nullptr;     // [n] or null
+
+  // per-run buffers
+  int cap_R = 0;             // replicas the buffers hold
+  int R = 0, t_f = 0;        // current run
+  uint64_t seed = 0;
+  bool state_valid = false;
+  bool result_valid = false;
+  int traj_iters = 0;        // iterations recorded by the last call
+  void* d_state = nullptr;   // [R][n] acc_t
+  int8_t* d_spins = nullptr; // [R][n]
+  double* d_E = nullptr;     // [R]
+  long long* d_Eint = nullptr;
+  void* d_S[2] = {nullptr, nullptr};  // per-iteration path: [Rp][Kp] op_t
+  int cap_Rp = 0;
+  void* d_traj = nullptr;
+  size_t traj_cap = 0;
+  void* d_coef = nullptr;
+  int coef_tf = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
+  int launches = 0;
+  bool timed = false;
+
+  size_t acc_size() const { return prec == NMFA_FP64 ? 8 : 4; }
+  size_t op_size() const { return prec == NMFA_FP64 ? 8 : (prec == NMFA_FP32 ? 4 : 2); }
+};
+
+static void free_run_buffers(nmfa_ctx* c) {
+  (void)hipFree(c->d_state);
+  (void)hipFree(c->d_spins);
+  (void)hipFree(c->d_E);
+  (void)hipFree(c->d_Eint);
+  (void)hipFree(c->d_S[0]);
+  (void)hipFree(c->d_S[1]);
+  c->d_state = nullptr;
+  c->d_spins = nullptr;
+  c->d_E = nullptr;
+  c->d_Eint = nullptr;
+  c->d_S[0] = c->d_S[1] = nullptr;
+  c->cap_R = 0;
+  c->cap_Rp = 0;
+}
+
+extern "C" void nmfa_params_default(nmfa_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(nmfa_params);
+  p->precision = NMFA_BF16;
+  p->alpha = 0.15;
+  p->sigma = 0.15;
+  p->n_knots = 0;
+  p->flags = 0;
+  p->record_iters = 0;
+}
+
+extern "C" void nmfa_destroy(nmfa_ctx* c) {
+  if (!c) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  free_run_buffers(c);
+  (void)hipFree(c->d_J);
+  (void)hipFree(c->d_inv);
+  (void)hipFree(c->d_hterm);
+  (void)hipFree(c->d_J8);
+  (void)hipFree(c->d_J64);
+  (void)hipFree(c->d_h);
+  (void)hipFree(c->d_traj);
+  (void)hipFree(c->d_coef);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->evm) (void)hipEventDestroy(c->evm);
+  (void)hipSetDevice(prev);
+  delete c;
+}
+
+static int device_max_lds() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+  return v;
+}
+
+extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nmfa_params* p,
+                           nmfa_ctx** out) {
+  if (!out) return fail(NMFA_EINVAL, "nmfa_create: out is NULL");
+  *out = nullptr;
+  nmfa_params dp;
+  nmfa_params_default(&dp);
+  if (!p) p = &dp;
+  if (p->struct_size != sizeof(nmfa_params))
+    return fail(NMFA_EINVAL, "nmfa_create: params.struct_size %u != %zu", p->struct_size, sizeof(nmfa_params));
+  if (n < 1 || n > 16384) return fail(NMFA_EINVAL, "nmfa_create: n = %d outside [1, 16384]", n);
+  if (!J) return fail(NMFA_EINVAL, "nmfa_create: J is NULL");
+  if (p->precision > NMFA_FP8J_BF16S) return fail(NMFA_EINVAL, "nmfa_create: unknown precision %u", p->precision);
+  if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return fail(NMFA_EINVAL, "nmfa_create: alpha must be in (0, 1]");
+  if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return fail(NMFA_EINVAL, "nmfa_create: sigma must be >= 0");
+  if (p->record_iters < 0) return fail(NMFA_EINVAL, "nmfa_create: record_iters < 0");
+
+  // schedule knots
+  std::vector<double> ku, kT;
+  if (p->n_knots == 0) {
+    ku.assign(kDefaultKnotU, kDefaultKnotU + 4);
+    kT.assign(kDefaultKnotT, kDefaultKnotT + 4);
+  } else {
+    if (p->n_knots < 0 || !p->knot_T || (p->n_knots > 1 && !p->knot_u))
+      return fail(NMFA_EINVAL, "nmfa_create: invalid schedule knots");
+    for (int k = 0; k < p->n_knots; ++k) {
+      if (!(p->knot_T[k] > 0.0) || !std::isfinite(p->knot_T[k]))
+        return fail(NMFA_EINVAL, "nmfa_create: knot temperature %d is not > 0", k);
+      kT.push_back(p->knot_T[k]);
+      ku.push_back(p->n_knots > 1 ? p->knot_u[k] : 0.0);
+      if (k > 0 && !(ku[k] > ku[k - 1])) return fail(NMFA_EINVAL, "nmfa_create: knot positions must increase");
+    }
+    if (p->n_knots > 1 && (ku.front() != 0.0 || ku.back() != 1.0))
+      return fail(NMFA_EINVAL, "nmfa_create: knot positions must start at 0 and end at 1");
+  }
+
+  // couplings: symmetrise if given as an upper triangle, validate
+  const size_t nn = (size_t)n * n;
+  std::vector<double> Jf(nn);
+  const bool upper = (p->flags & NMFA_FLAG_UPPER_TRIANGULAR) != 0;
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      double v;
+      if (upper) v = (i < j) ? J[(size_t)i * n + j] : (i > j ? J[(size_t)j * n + i] : 0.0);
+      else v = J[(size_t)i * n + j];
+      if (!std::isfinite(v)) return fail(NMFA_EINVAL, "nmfa_create: J[%d][%d] is not finite", i, j);
+      Jf[(size_t)i * n + j] = v;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    if (Jf[(size_t)i * n + i] != 0.0) return fail(NMFA_EINVAL, "nmfa_create: J[%d][%d] != 0 (diagonal)", i, i);
+    for (int j = i + 1; j < n; ++j)
+      if (Jf[(size_t)i * n + j] != Jf[(size_t)j * n + i])
+        return fail(NMFA_EINVAL, "nmfa_create: J is not symmetric at (%d, %d)", i, j);
+  }
+  if (h)
+    for (int i = 0; i < n; ++i)
+      if (!std::isfinite(h[i])) return fail(NMFA_EINVAL, "nmfa_create: h[%d] is not finite", i);
+
+  nmfa_ctx* c = new nmfa_ctx();
+  c->n = n;
+  c->prec = (int)p->precision;
+  c->alpha = p->alpha;
+  c->sigma = p->sigma;
+  c->flags = p->flags;
+  c->record = p->record_iters;
+  c->ku = ku;
+  c->kT = kT;
+  (void)hipGetDevice(&c->device);
+  bool any_h = false;
+  if (h) {
+    c->h.assign(h, h + n);
+    for (int i = 0; i < n; ++i) {
+      if (h[i] != 0.0) any_h = true;
+      if (!is_integral(h[i])) c->h_integral = false;
+    }
+  }
+  c->has_h = any_h;
+  if (!any_h) c->h.clear();
+  c->J_integral = true;
+  int Jmax = 0;
+  for (size_t k = 0; k < nn; ++k) {
+    if (!is_integral(Jf[k])) {
+      c->J_integral = false;
+      break;
+    }
+    Jmax = std::max(Jmax, (int)std::min(std::fabs(Jf[k]), 1e9));
+  }
+  const bool use_J8 = c->J_integral && Jmax <= 127;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) c->w_total += Jf[(size_t)i * n + j];
+
+  // kernel path and padded layout
+  const size_t es = c->op_size();
+  const bool bf = (c->prec == NMFA_BF16 || c->prec == NMFA_FP8J_BF16S);
+  const int Mp_s = (int)round_up(n, 16);
+  const int Kp_s = (int)round_up(n, bf ? 32 : 16);
+  const int stride_s = (int)((round_up(Kp_s * es, 256) + 16) / es);
+  const bool small_fits = Mp_s <= 256 && small_lds_bytes(c->prec, Mp_s, stride_s) <= (size_t)device_max_lds();
+  if (small_fits && !(p->flags & NMFA_FLAG_FORCE_STEP)) {
+    c->path = 0;
+    c->Mp = Mp_s;
+    c->Kp = Kp_s;
+    c->lds_stride = stride_s;
+  } else {
+    c->path = 1;
+    c->Mp = (int)round_up(n, 64);
+    c->Kp = c->Mp;
+    c->lds_stride = 0;
+  }
+  const int Mp = c->Mp, Kp = c->Kp;
+
+  // normalisers sqrt(h_i^2 + sum_j J_ij^2) in FP64; a zero normaliser gives inv = 0
+  std::vector<double> inv(Mp, 0.0), hterm(Mp, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const double hi = any_h ? h[i] : 0.0;
+    double acc = hi * hi;
+    for (int j = 0; j < n; ++j) acc += Jf[(size_t)i * n + j] * Jf[(size_t)i * n + j];
+    const double nrm = std::sqrt(acc);
+    inv[i] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    hterm[i] = (c->prec == NMFA_FP64) ? hi : hi * inv[i];
+  }
+
+  // operand copy of J
+  const bool j8_small = (c->prec == NMFA_FP8J_BF16S && c->path == 0);
+  const size_t jbytes = (size_t)Mp * Kp * (j8_small ? 1 : es);
+  std::vector<unsigned char> jbuf(jbytes, 0);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      const double v = Jf[(size_t)i * n + j];
+      const size_t idx = (size_t)i * Kp + j;
+      if (j8_small) {
+        jbuf[idx] = fp8e4m3_bits(v);
+      } else if (c->prec == NMFA_FP64) {
+        std::memcpy(&jbuf[idx * 8], &v, 8);
+      } else if (c->prec == NMFA_FP32) {
+        const float f = (float)v;
+        std::memcpy(&jbuf[idx * 4], &f, 4);
+      } else {
+        // BF16, and FP8 J on the per-iteration path: FP8-rounded values widened to BF16
+        double w = v;
+        if (c->prec == NMFA_FP8J_BF16S) {
+          const uint8_t b = fp8e4m3_bits(v);
+          const int e = (b >> 3) & 0xf, m = b & 7;
+          w = (e == 0) ? std::ldexp((double)m, -9) : std::ldexp(1.0 + m / 8.0, e - 7);
+          if (b & 0x80) w = -w;
+        }
+        const uint16_t bits = bf16_bits(w);
+        std::memcpy(&jbuf[idx * 2], &bits, 2);
+      }
+    }
+  }
+
+  auto cleanup_fail = [&](int code) {
+    nmfa_destroy(c);
+    return code;
+  };
+#define CREATE_TRY(expr)                                                                            \
+  do {                                                                                              \
+    hipError_t _e = (expr);                                                                         \
+    if (_e != hipSuccess)                                                                           \
+      return cleanup_fail(fail(_e == hipErrorOutOfMemory ? NMFA_ENOMEM : NMFA_EDEVICE, "%s failed: %s", \
+                               #expr, hipGetErrorString(_e)));                                      \
+  } while (0)
+
+  CREATE_TRY(hipMalloc(&c->d_J, jbytes));
+  CREATE_TRY(hipMemcpy(c->d_J, jbuf.data(), jbytes, hipMemcpyHostToDevice));
+  const size_t as = c->acc_size();
+  CREATE_TRY(hipMalloc(&c->d_inv, Mp * as));
+  CREATE_TRY(hipMalloc(&c->d_hterm, Mp * as));
+  if (c->prec == NMFA_FP64) {
+    CREATE_TRY(hipMemcpy(c->d_inv, inv.data(), Mp * 8, hipMemcpyHostToDevice));
+    CREATE_TRY(hipMemcpy(c->d_hterm, hterm.data(), Mp * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> fi(Mp), fh(Mp);
+    for (int i = 0; i < Mp; ++i) {
+      fi[i] = (float)inv[i];
+      fh[i] = (float)hterm[i];
+    }
+    CREATE_TRY(hipMemcpy(c->d_inv, fi.data(), Mp * 4, hipMemcpyHostToDevice));
+    CREATE_TRY(hipMemcpy(c->d_hterm, fh.data(), Mp * 4, hipMemcpyHostToDevice));
+  }
+  if (use_J8) {
+    std::vector<int8_t> j8(nn);
+    for (size_t k = 0; k < nn; ++k) j8[k] = (int8_t)Jf[k];
+    CREATE_TRY(hipMalloc(&c->d_J8, nn));
+    CREATE_TRY(hipMemcpy(c->d_J8, j8.data(), nn, hipMemcpyHostToDevice));
+  } else {
+    CREATE_TRY(hipMalloc(&c->d_J64, nn * 8));
+    CREATE_TRY(hipMemcpy(c->d_J64, Jf.data(), nn * 8, hipMemcpyHostToDevice));
+  }
+  if (any_h) {
+    CREATE_TRY(hipMalloc(&c->d_h, n * 8));
+    CREATE_TRY(hipMemcpy(c->d_h, c->h.data(), n * 8, hipMemcpyHostToDevice));
+  }
+  CREATE_TRY(hipEventCreate(&c->ev0));
+  CREATE_TRY(hipEventCreate(&c->ev1));
+  CREATE_TRY(hipEventCreate(&c->evm));
+#undef CREATE_TRY
+  *out = c;
+  return NMFA_OK;
+}
+
+// Make sure the per-run buffers hold R replicas (contents are kept only if R is unchanged).
+static int ensure_run_buffers(nmfa_ctx* c, int R) {
+  const int Rp = (int)round_up(R, 64);
+  if (R > c->cap_R) {
+    free_run_buffers(c);
+    const size_t cnt = (size_t)R * c->n;
+    HIP_TRY(hipMalloc(&c->d_state, cnt * c->acc_size()));
+    HIP_TRY(hipMalloc(&c->d_spins, cnt));
+    HIP_TRY(hipMalloc(&c->d_E, (size_t)R * 8));
+    HIP_TRY(hipMalloc(&c->d_Eint, (size_t)R * 8));
+    c->cap_R = R;
+    c->state_valid = false;
+  }
+  if (c->path == 1 && Rp > c->cap_Rp) {
+    (void)hipFree(c->d_S[0]);
+    (void)hipFree(c->d_S[1]);
+    c->d_S[0] = c->d_S[1] = nullptr;
+    const size_t sb = (size_t)Rp * c->Kp * c->op_size();
+    HIP_TRY(hipMalloc(&c->d_S[0], sb));
+    HIP_TRY(hipMalloc(&c->d_S[1], sb));
+    c->cap_Rp = Rp;
+  }
+  return NMFA_OK;
+}
+
+static int ensure_coef(nmfa_ctx* c, int t_f) {
+  if (c->coef_tf == t_f && c->d_coef) return NMFA_OK;
+  (void)hipFree(c->d_coef);
+  c->d_coef = nullptr;
+  c->coef_tf = 0;
+  const double two_log2e = 2.0 / std::log(2.0);
+  if (c->prec == NMFA_FP64) {
+    std::vector<double> v(t_f);
+    for (int t = 1; t <= t_f; ++t) v[t - 1] = 1.0 / schedule_T(c->ku, c->kT, t, t_f);
+    HIP_TRY(hipMalloc(&c->d_coef, (size_t)t_f * 8));
+    HIP_TRY(hipMemcpy(c->d_coef, v.data(), (size_t)t_f * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> v(t_f);
+    for (int t = 1; t <= t_f; ++t) v[t - 1] = (float)(two_log2e / schedule_T(c->ku, c->kT, t, t_f));
+    HIP_TRY(hipMalloc(&c->d_coef, (size_t)t_f * 4));
+    HIP_TRY(hipMemcpy(c->d_coef, v.data(), (size_t)t_f * 4, hipMemcpyHostToDevice));
+  }
+  c->coef_tf = t_f;
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_anneal_range(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end,
+                                 uint64_t seed, void* hip_stream) {
+  if (!c) return fail(NMFA_EINVAL, "nmfa_anneal: context is NULL");
+  if (R < 1 || R > (1 << 24)) return fail(NMFA_EINVAL, "nmfa_anneal: R = %d outside [1, 2^24]", R);
+  if (t_f < 1) return fail(NMFA_EINVAL, "nmfa_anneal: t_f = %d < 1", t_f);
+  if (t_begin < 1 || t_end < t_begin || t_end > t_f)
+    return fail(NMFA_EINVAL, "nmfa_anneal: need 1 <= t_begin (%d) <= t_end (%d) <= t_f (%d)", t_begin, t_end, t_f);
+  if (t_begin > 1 && !(c->state_valid && c->R == R))
+    return fail(NMFA_ESTATE, "nmfa_anneal: t_begin > 1 needs the state of a previous call with R = %d", R);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc;
+  if (c->R != R && c->cap_R >= R && t_begin == 1) c->state_valid = false;
+  if ((rc = ensure_run_buffers(c, R)) != NMFA_OK) return rc;
+  if ((rc = ensure_coef(c, t_f)) != NMFA_OK) return rc;
+  const int iters = t_end - t_begin + 1;
+  const int rec = std::min(c->record, iters);
+  if (rec > 0) {
+    const size_t need = (size_t)rec * R * c->n * c->acc_size();
+    if (need > c->traj_cap) {
+      (void)hipFree(c->d_traj);
+      c->d_traj = nullptr;
+      c->traj_cap = 0;
+      HIP_TRY(hipMalloc(&c->d_traj, need));
+      c->traj_cap = need;
+    }
+  }
+  c->R = R;
+  c->t_f = t_f;
+  c->seed = seed;
+  c->stream = st;
+  c->result_valid = false;
+
+  AnnealArgs a{};
+  a.J = c->d_J;
+  a.inv_norm = c->d_inv;
+  a.hterm = c->d_hterm;
+  a.coef = c->d_coef;
+  a.state = c->d_state;
+  a.spins = c->d_spins;
+  a.traj = rec > 0 ? c->d_traj : nullptr;
+  a.record = rec;
+  a.N = c->n;
+  a.Mp = c->Mp;
+  a.Kp = c->Kp;
+  a.R = R;
+  a.Rp = (int)round_up(R, 64);
+  a.lds_stride = c->lds_stride;
+  a.t_begin = t_begin;
+  a.t_end = t_end;
+  a.load_state = (t_begin > 1) ? 1 : 0;
+  a.key0 = (uint32_t)(seed & 0xffffffffu);
+  a.key1 = (uint32_t)(seed >> 32);
+  a.alpha = c->alpha;
+  a.sigma = c->sigma;
+  a.negate_noise = (c->flags & NMFA_FLAG_NEGATE_NOISE) ? 1 : 0;
+
+  HIP_TRY(hipEventRecord(c->ev0, st));
+  if (c->path == 0) {
+    HIP_TRY(launch_anneal_small(c->prec, a, st));
+    c->launches = 1;
+    HIP_TRY(hipEventRecord(c->evm, st));
+  } else {
+    if (t_begin == 1) HIP_TRY(hipMemsetAsync(c->d_state, 0, (size_t)R * c->n * c->acc_size(), st));
+    HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[0], c->n, R, c->Kp, a.Rp, t_begin == 1 ? 1 : 0, st));
+    HIP_TRY(hipEventRecord(c->ev0, st));
+    int cur = 0;
+    for (int t = t_begin; t <= t_end; ++t) {
+      HIP_TRY(launch_anneal_step(c->prec, a, c->d_S[cur], c->d_S[cur ^ 1], t, st));
+      cur ^= 1;
+    }
+    c->launches = t_end - t_begin + 1;
+    HIP_TRY(hipEventRecord(c->evm, st));
+    HIP_TRY(launch_readout(c->prec, c->d_state, c->d_spins, (size_t)R * c->n, st));
+  }
+  HIP_TRY(launch_energy(c->d_J8, c->d_J64, c->d_h, c->h_integral ? 1 : 0, c->d_spins, c->n, R, c->d_Eint,
+                        c->d_E, st));
+  HIP_TRY(hipEventRecord(c->ev1, st));
+  c->timed = true;
+  c->state_valid = true;
+  c->result_valid = true;
+  c->traj_iters = rec;
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_anneal(nmfa_ctx* c, int32_t R, int32_t t_f, uint64_t seed, void* hip_stream) {
+  return nmfa_anneal_range(c, R, t_f, 1, t_f, seed, hip_stream);
+}
+
+static int sync_ctx(nmfa_ctx* c) {
+  HIP_TRY(hipSetDevice(c->device));
+  if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
+  else HIP_TRY(hipDeviceSynchronize());
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_spins(nmfa_ctx* c, int8_t* out, int32_t on_device) {
+  if (!c || !out) return fail(NMFA_EINVAL, "nmfa_spins: NULL argument");
+  if (!c->result_valid) return fail(NMFA_ESTATE, "nmfa_spins: no anneal has run");
+  int rc = sync_ctx(c);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(out, c->d_spins, (size_t)c->R * c->n,
+                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_energies(nmfa_ctx* c, double* E, int64_t* E_int) {
+  if (!c || !E) return fail(NMFA_EINVAL, "nmfa_energies: NULL argument");
+  if (!c->result_valid) return fail(NMFA_ESTATE, "nmfa_energies: no anneal has run");
+  int rc = sync_ctx(c);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(E, c->d_E, (size_t)c->R * 8, hipMemcpyDeviceToHost));
+  if (E_int) {
+    if (c->J_integral && c->h_integral && c->d_J8) {
+      HIP_TRY(hipMemcpy(E_int, c->d_Eint, (size_t)c->R * 8, hipMemcpyDeviceToHost));
+    } else {
+      std::memset(E_int, 0, (size_t)c->R * 8);
+    }
+  }
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_cuts(nmfa_ctx* c, double* cut) {
+  if (!c || !cut) return fail(NMFA_EINVAL, "nmfa_cuts: NULL argument");
+  std::vector<double> E(c->R > 0 ? c->R : 1);
+  int rc = nmfa_energies(c, E.data(), nullptr);
+  if (rc) return rc;
+  for (int r = 0; r < c->R; ++r) cut[r] = (c->w_total - E[r]) / 2.0;
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_energies_of(nmfa_ctx* c, int32_t R, const int8_t* spins, double* E, int64_t* E_int) {
+  if (!c || !spins || !E || R < 1) return fail(NMFA_EINVAL, "nmfa_energies_of: invalid argument");
+  for (size_t k = 0; k < (size_t)R * c->n; ++k)
+    if (spins[k] != 1 && spins[k] != -1) return fail(NMFA_EINVAL, "nmfa_energies_of: spins must be +1/-1");
+  HIP_TRY(hipSetDevice(c->device));
+  int8_t* d_s = nullptr;
+  double* d_E = nullptr;
+  long long* d_Ei = nullptr;
+  const size_t cnt = (size_t)R * c->n;
+  hipError_t e = hipMalloc(&d_s, cnt);
+  if (e == hipSuccess) e = hipMalloc(&d_E, (size_t)R * 8);
+  if (e == hipSuccess) e = hipMalloc(&d_Ei, (size_t)R * 8);
+  if (e == hipSuccess) e = hipMemcpy(d_s, spins, cnt, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_energy(c->d_J8, c->d_J64, c->d_h, c->h_integral ? 1 : 0, d_s, c->n, R, d_Ei, d_E, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(E, d_E, (size_t)R * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && E_int) {
+    if (c->J_integral && c->h_integral && c->d_J8) e = hipMemcpy(E_int, d_Ei, (size_t)R * 8, hipMemcpyDeviceToHost);
+    else std::memset(E_int, 0, (size_t)R * 8);
+  }
+  (void)hipFree(d_s);
+  (void)hipFree(d_E);
+  (void)hipFree(d_Ei);
+  if (e != hipSuccess) return fail(NMFA_EDEVICE, "nmfa_energies_of: %s", hipGetErrorString(e));
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_get_state(nmfa_ctx* c, double* out) {
+  if (!c || !out) return fail(NMFA_EINVAL, "nmfa_get_state: NULL argument");
+  if (!c->state_valid) return fail(NMFA_ESTATE, "nmfa_get_state: no state");
+  int rc = sync_ctx(c);
+  if (rc) return rc;
+  const size_t cnt = (size_t)c->R * c->n;
+  if (c->prec == NMFA_FP64) {
+    HIP_TRY(hipMemcpy(out, c->d_state, cnt * 8, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(cnt);
+    HIP_TRY(hipMemcpy(f.data(), c->d_state, cnt * 4, hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < cnt; ++k) out[k] = f[k];
+  }
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_set_state(nmfa_ctx* c, int32_t R, const double* in) {
+  if (!c || !in || R < 1) return fail(NMFA_EINVAL, "nmfa_set_state: invalid argument");
+  const size_t cnt = (size_t)R * c->n;
+  for (size_t k = 0; k < cnt; ++k)
+    if (!(std::fabs(in[k]) <= 1.0)) return fail(NMFA_EINVAL, "nmfa_set_state: state values must lie in [-1, 1]");
+  HIP_TRY(hipSetDevice(c->device));
+  int rc = sync_ctx(c);
+  if (rc) return rc;
+  if ((rc = ensure_run_buffers(c, R)) != NMFA_OK) return rc;
+  if (c->prec == NMFA_FP64) {
+    HIP_TRY(hipMemcpy(c->d_state, in, cnt * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(cnt);
+    for (size_t k = 0; k < cnt; ++k) f[k] = (float)in[k];
+    HIP_TRY(hipMemcpy(c->d_state, f.data(), cnt * 4, hipMemcpyHostToDevice));
+  }
+  c->R = R;
+  c->state_valid = true;
+  c->result_valid = false;
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_trajectory(nmfa_ctx* c, double* out) {
+  if (!c || !out) return fail(NMFA_EINVAL, "nmfa_trajectory: NULL argument");
+  if (!c->result_valid || c->traj_iters <= 0) return fail(NMFA_ESTATE, "nmfa_trajectory: nothing recorded");
+  int rc = sync_ctx(c);
+  if (rc) return rc;
+  const size_t cnt = (size_t)c->traj_iters * c->R * c->n;
+  if (c->prec == NMFA_FP64) {
+    HIP_TRY(hipMemcpy(out, c->d_traj, cnt * 8, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(cnt);
+    HIP_TRY(hipMemcpy(f.data(), c->d_traj, cnt * 4, hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < cnt; ++k) out[k] = f[k];
+  }
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_info(nmfa_ctx* c, int32_t* n, int32_t* precision, int32_t* path) {
+  if (!c) return fail(NMFA_EINVAL, "nmfa_info: context is NULL");
+  if (n) *n = c->n;
+  if (precision) *precision = c->prec;
+  if (path) *path = c->path;
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_last_timing(nmfa_ctx* c, double* anneal_ms, double* total_ms, int32_t* launches) {
+  if (!c) return fail(NMFA_EINVAL, "nmfa_last_timing: context is NULL");
+  if (!c->timed) return fail(NMFA_ESTATE, "nmfa_last_timing: no anneal has run");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipEventSynchronize(c->ev1));
+  float fa = 0.f, ft = 0.f;
+  HIP_TRY(hipEventElapsedTime(&fa, c->ev0, c->evm));
+  HIP_TRY(hipEventElapsedTime(&ft, c->ev0, c->ev1));
+  if (anneal_ms) *anneal_ms = fa;
+  if (total_ms) *total_ms = ft;
+  if (launches) *launches = c->launches;
+  return NMFA_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Noise utilities
+// ------------------------------------------------------------------------------------------
+extern "C" int nmfa_noise_words(uint64_t seed, int32_t t, int32_t r0, int32_t n_rep, int32_t n_quads, uint32_t* out) {
+  if (!out || t < 0 || r0 < 0 || n_rep < 1 || n_quads < 1 || (int64_t)n_rep * n_quads > (1 << 26))
+    return fail(NMFA_EINVAL, "nmfa_noise_words: invalid argument");
+  const size_t cnt = (size_t)n_rep * n_quads * 4;
+  uint32_t* d = nullptr;
+  HIP_TRY(hipMalloc(&d, cnt * 4));
+  hipError_t e = launch_noise_words((uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)t, (uint32_t)r0, n_rep, n_quads, d, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(out, d, cnt * 4, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(NMFA_EDEVICE, "nmfa_noise_words: %s", hipGetErrorString(e));
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_noise_values(uint64_t seed, int32_t t, int32_t r0, int32_t n_rep, int32_t n_quads, int32_t fp64,
+                                 double* out) {
+  if (!out || t < 0 || r0 < 0 || n_rep < 1 || n_quads < 1 || (int64_t)n_rep * n_quads > (1 << 26))
+    return fail(NMFA_EINVAL, "nmfa_noise_values: invalid argument");
+  const size_t cnt = (size_t)n_rep * n_quads * 4;
+  double* d = nullptr;
+  HIP_TRY(hipMalloc(&d, cnt * 8));
+  hipError_t e = launch_noise_values((uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)t, (uint32_t)r0, n_rep, n_quads,
+                                     fp64 ? 1 : 0, d, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(out, d, cnt * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(NMFA_EDEVICE, "nmfa_noise_values: %s", hipGetErrorString(e));
+  return NMFA_OK;
+}

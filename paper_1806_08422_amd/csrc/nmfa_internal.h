@@ -1,0 +1,43 @@
+// Internal interface between the C-ABI layer (nmfa_api.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nmfa {
+
+// Arguments of one anneal launch (passed by value to the kernels).
+struct AnnealArgs {
+  const void* J;         // couplings, [Mp][Kp] row-major in the operand type (FP8 bytes for J8)
+  const void* inv_norm;  // [Mp] 1/sqrt(h_i^2 + sum_j J_ij^2), 0 for padding and zero normalisers
+  const void* hterm;     // [Mp] FP64 path: h_i; FP32/BF16 paths: h_i * inv_norm_i
+  const void* coef;      // [t_f] FP64 path: 1/T_t; FP32/BF16 paths: 2 log2(e) / T_t
+  void* state;           // [R][N] master state (FP64 or FP32), in/out
+  int8_t* spins;         // [R][N] sign readout, or null
+  void* traj;            // [record][R][N] master-precision trajectory, or null
+  int record;            // number of iterations recorded, counted from t_begin
+  int N, Mp, Kp, R, Rp;  // spins, padded rows, padded k, replicas, padded replicas
+  int lds_stride;        // LDS row stride in elements (persistent kernel)
+  int t_begin, t_end;    // iterations run, 1-based, inclusive
+  int load_state;        // 1: continue from `state`; 0: start from s = 0
+  uint32_t key0, key1;   // Philox key = 64-bit seed
+  double alpha, sigma;
+  int negate_noise;      // test hook: z -> -z
+};
+
+hipError_t launch_anneal_small(int prec, const AnnealArgs& a, hipStream_t st);
+size_t small_lds_bytes(int prec, int Mp, int stride);
+hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
+                              hipStream_t st);
+hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R, int Kp, int Rp, int zero,
+                             hipStream_t st);
+hipError_t launch_readout(int prec, const void* state, int8_t* spins, size_t count, hipStream_t st);
+hipError_t launch_energy(const int8_t* J8, const double* J64, const double* h, int h_integral,
+                         const int8_t* spins, int N, int R, long long* E_int, double* E, hipStream_t st);
+hipError_t launch_noise_words(uint32_t k0, uint32_t k1, uint32_t t, uint32_t r0, int nrep, int nq,
+                              uint32_t* out, hipStream_t st);
+hipError_t launch_noise_values(uint32_t k0, uint32_t k1, uint32_t t, uint32_t r0, int nrep, int nq,
+                               int fp64, double* out, hipStream_t st);
+
+}  // namespace nmfa

@@ -1,0 +1,564 @@
+// NMFA hot-path kernels for gfx950.
+//
+// One iteration of Algorithm 1 (paper Sec. II) for every spin i and replica r:
+//   Phi_i = (h_i + sum_j J_ij s_j) / sqrt(h_i^2 + sum_j J_ij^2) + N(0, sigma)
+//   s^_i  = -tanh(Phi_i / T_t)
+//   s_i  <- alpha s^_i + (1 - alpha) s_i          (after all s^ of the iteration are known)
+// The contraction sum_j J_ij s_j over all replicas is the matrix product J . S and runs on
+// MFMA; the normalisation, noise, Boltzmann factor and damped update are fused into the MFMA
+// epilogue in registers. After the last iteration the sign readout s~_i = s_i/|s_i| and the
+// energy of Eq. 1 are evaluated.
+//
+// Kernels:
+//   anneal_small<P>   persistent: one workgroup owns 16 replicas and all N <= 256 spins for the
+//                     whole anneal. J sits in LDS, the operand copy of S is double-buffered in
+//                     LDS, the master state lives in registers; one barrier per iteration.
+//   anneal_step<P>    one iteration for large N: each wave owns 16 rows x 64 replicas, reads
+//                     J and S straight from global memory (L2), updates the master state in
+//                     HBM and writes the next operand copy of S.
+//   readout_kernel    s~ = sign(s) (s = 0 reads +1).
+//   energy_kernel     exact integer energies for integral J (int8) and integral h, or an
+//                     integral pair term plus an FP64 field term summed in ascending i.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "nmfa_device.h"
+#include "nmfa_internal.h"
+
+namespace nmfa {
+
+// ------------------------------------------------------------------------------------------
+// Shared epilogue: from the accumulated field of four consecutive rows of one replica to the
+// updated master state. acc[v] = sum_j J_ij s_j for row i = row0 + v.
+// ------------------------------------------------------------------------------------------
+template <int P>
+struct Epilogue;
+
+template <>
+struct Epilogue<PREC_FP64> {
+  __device__ static __forceinline__ void apply(const double acc[4], const double inv[4],
+                                               const double h[4], double s[4], const AnnealArgs& a,
+                                               double coef_t, uint32_t q, uint32_t r, uint32_t t) {
+    double z[4];
+    gauss4_f64(philox4x32_10(q, r, t, 0u, a.key0, a.key1), z);
+    const double sg = a.negate_noise ? -a.sigma : a.sigma;
+    const double oma = 1.0 - a.alpha;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double phi = (h[v] + acc[v]) * inv[v] + sg * z[v];
+      const double s_hat = -tanh(phi * coef_t);
+      s[v] = a.alpha * s_hat + oma * s[v];
+    }
+  }
+};
+
+template <int P>
+struct EpilogueF32 {
+  __device__ static __forceinline__ void apply(const float acc[4], const float inv[4],
+                                               const float hinv[4], float s[4], const AnnealArgs& a,
+                                               float coef_t, uint32_t q, uint32_t r, uint32_t t) {
+    float z[4];
+    const float sg = (float)a.sigma;
+    sigma_gauss4_f32(philox4x32_10(q, r, t, 0u, a.key0, a.key1), -2.0f * 0.6931471805599453f * sg * sg,
+                     z);
+    const float alpha = (float)a.alpha;
+    const float oma = (float)(1.0 - a.alpha);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float x = fmaf(acc[v], inv[v], hinv[v]);
+      const float phi = a.negate_noise ? x - z[v] : x + z[v];
+      const float s_hat = neg_tanh_from_exp2_arg(phi * coef_t);
+      s[v] = fmaf(alpha, s_hat, oma * s[v]);
+    }
+  }
+};
+template <>
+struct Epilogue<PREC_FP32> : EpilogueF32<PREC_FP32> {};
+template <>
+struct Epilogue<PREC_BF16> : EpilogueF32<PREC_BF16> {};
+
+// ------------------------------------------------------------------------------------------
+// anneal_small<P, J8>: see the file header. Block = 64 * (Mp/16) threads, wave w owns rows
+// [16w, 16w+16); grid = ceil(R / 16) workgroups, workgroup b owns replicas [16b, 16b+16).
+// LDS: Js[Mp][js] (op_t), Ss[2][16][js] (op_t), with js = padded row stride in elements.
+// J8: the global copy of J is FP8 e4m3 and is widened to BF16 while it is staged into LDS.
+// ------------------------------------------------------------------------------------------
+template <int P, bool J8>
+__global__ __launch_bounds__(1024) void anneal_small(AnnealArgs a) {
+  using Tr = Traits<P>;
+  using op_t = typename Tr::op_t;
+  using acc_t = typename Tr::acc_t;
+  using frag_t = typename Tr::frag_t;
+  using acc4_t = typename Tr::acc4_t;
+  constexpr int KW = Tr::KW;
+  constexpr int VEC = 16 / (KW * (int)sizeof(op_t));  // MFMA steps per 16-byte LDS read
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = a.N, Mp = a.Mp, Kp = a.Kp, js = a.lds_stride;
+  op_t* Js = reinterpret_cast<op_t*>(smem);
+  op_t* Ss = Js + (size_t)Mp * js;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  const int r = blockIdx.x * 16 + c;  // replica of this lane
+  const int row0 = wave * 16 + 4 * g;  // first of this lane's four rows (accumulator layout)
+  const int arow = wave * 16 + Tr::a_row(c);  // row this lane supplies to the A operand
+  const int Kq = Kp >> 2;
+
+  // ---- stage J into LDS (16-byte chunks), zero both S buffers --------------------------------
+  {
+    const int chunks_per_row = (Kp * (int)sizeof(op_t)) / 16;
+    const int total = Mp * chunks_per_row;
+    for (int ch = tid; ch < total; ch += blockDim.x) {
+      const int row = ch / chunks_per_row;
+      const int cc = ch - row * chunks_per_row;
+      uint4 v;
+      if constexpr (J8) {
+        const uint8_t* src = reinterpret_cast<const uint8_t*>(a.J) + (size_t)row * Kp + cc * 8;
+        const uint2 raw = *reinterpret_cast<const uint2*>(src);
+        __bf16 w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t byte = ((k < 4 ? raw.x : raw.y) >> (8 * (k & 3))) & 0xffu;
+          w[k] = (__bf16)fp8e4m3_to_float(byte);
+        }
+        v = *reinterpret_cast<const uint4*>(w);
+      } else {
+        v = reinterpret_cast<const uint4*>(a.J)[(size_t)row * chunks_per_row + cc];
+      }
+      *reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(Js + (size_t)row * js) + cc * 16) = v;
+    }
+    const int s_words = (2 * 16 * js * (int)sizeof(op_t)) / 4;
+    uint32_t* Sw = reinterpret_cast<uint32_t*>(Ss);
+    for (int k = tid; k < s_words; k += blockDim.x) Sw[k] = 0u;
+  }
+
+  // ---- per-lane constants and initial state ----------------------------------------------
+  acc_t inv[4], hv[4], s[4];
+  const acc_t* inv_g = reinterpret_cast<const acc_t*>(a.inv_norm);
+  const acc_t* h_g = reinterpret_cast<const acc_t*>(a.hterm);
+  acc_t* state = reinterpret_cast<acc_t*>(a.state);
+  const bool live_r = r < a.R;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    inv[v] = inv_g[row0 + v];
+    hv[v] = h_g[row0 + v];
+    const bool live = live_r && (row0 + v) < N;
+    s[v] = (a.load_state && live) ? state[(size_t)r * N + row0 + v] : (acc_t)0;
+  }
+  __syncthreads();
+  if (a.load_state) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ss[(size_t)c * js + row0 + v] = (op_t)s[v];
+  }
+  __syncthreads();
+
+  const acc_t* coef = reinterpret_cast<const acc_t*>(a.coef);
+  acc_t* traj = reinterpret_cast<acc_t*>(a.traj);
+  int cur = 0;
+  for (int t = a.t_begin; t <= a.t_end; ++t) {
+    // ---- mean field: D = J[rows of this wave] . S[:, replicas of this block] ----------------
+    acc4_t acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = (acc_t)0;
+    const op_t* Arow = Js + (size_t)arow * js + g * Kq;
+    const op_t* Bcol = Ss + (size_t)cur * 16 * js + (size_t)c * js + g * Kq;
+    for (int m = 0; m < Kq; m += VEC * KW) {
+      const uint4 av = *reinterpret_cast<const uint4*>(Arow + m);
+      const uint4 bv = *reinterpret_cast<const uint4*>(Bcol + m);
+      const frag_t* af = reinterpret_cast<const frag_t*>(&av);
+      const frag_t* bf = reinterpret_cast<const frag_t*>(&bv);
+#pragma unroll
+      for (int u = 0; u < VEC; ++u) acc = Tr::mfma(af[u], bf[u], acc);
+    }
+    // ---- fused epilogue ------------------------------------------------------------------
+    acc_t fld[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fld[v] = acc[v];
+    Epilogue<P>::apply(fld, inv, hv, s, a, coef[t - 1], (uint32_t)(row0 >> 2), (uint32_t)r,
+                       (uint32_t)t);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (row0 + v >= N) s[v] = (acc_t)0;  // padding rows stay empty
+    const int nxt = cur ^ 1;
+    op_t* Sn = Ss + (size_t)nxt * 16 * js + (size_t)c * js + row0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Sn[v] = (op_t)s[v];
+    const int k = t - a.t_begin;
+    if (traj && k < a.record && live_r) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (row0 + v < N) traj[((size_t)k * a.R + r) * N + row0 + v] = s[v];
+    }
+    __syncthreads();
+    cur = nxt;
+  }
+
+  // ---- final state and sign readout -------------------------------------------------------
+  if (live_r) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (row0 + v < N) {
+        state[(size_t)r * N + row0 + v] = s[v];
+        if (a.spins) a.spins[(size_t)r * N + row0 + v] = (s[v] >= (acc_t)0) ? (int8_t)1 : (int8_t)-1;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// anneal_step<P>: one iteration t for large N. Block = 256 threads (4 waves); workgroup
+// (bx, by) owns rows [64 bx, 64 bx + 64) and replicas [64 by, 64 by + 64); wave w owns the 16
+// rows [64 bx + 16 w, +16) for all 64 replicas (four 16x16 MFMA tiles sharing one A fragment).
+// Operands come straight from global memory: J as [Mp][Kp] op_t, S_cur as [Rp][Kp] op_t
+// (replica-major, k contiguous). Writes S_next and the master state (in place).
+// ------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void anneal_step(AnnealArgs a, const void* S_cur_v, void* S_next_v,
+                                                   int t) {
+  using Tr = Traits<P>;
+  using op_t = typename Tr::op_t;
+  using acc_t = typename Tr::acc_t;
+  using frag_t = typename Tr::frag_t;
+  using acc4_t = typename Tr::acc4_t;
+  constexpr int KW = Tr::KW;
+  constexpr int VEC = 16 / (KW * (int)sizeof(op_t));
+  const op_t* J = reinterpret_cast<const op_t*>(a.J);
+  const op_t* S_cur = reinterpret_cast<const op_t*>(S_cur_v);
+  op_t* S_next = reinterpret_cast<op_t*>(S_next_v);
+  const int N = a.N, Kp = a.Kp, Kq = Kp >> 2;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  const int rowbase = blockIdx.x * 64 + wave * 16;
+  const int arow = rowbase + Tr::a_row(c);
+  const int row0 = rowbase + 4 * g;
+  const int rbase = blockIdx.y * 64;
+
+  acc4_t acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[ct][v] = (acc_t)0;
+
+  const op_t* Arow = J + (size_t)arow * Kp + g * Kq;
+  const op_t* B0 = S_cur + (size_t)(rbase + c) * Kp + g * Kq;
+  for (int m = 0; m < Kq; m += VEC * KW) {
+    const uint4 av = *reinterpret_cast<const uint4*>(Arow + m);
+    const frag_t* af = reinterpret_cast<const frag_t*>(&av);
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const uint4 bv = *reinterpret_cast<const uint4*>(B0 + (size_t)ct * 16 * Kp + m);
+      const frag_t* bf = reinterpret_cast<const frag_t*>(&bv);
+#pragma unroll
+      for (int u = 0; u < VEC; ++u) acc[ct] = Tr::mfma(af[u], bf[u], acc[ct]);
+    }
+  }
+
+  const acc_t* inv_g = reinterpret_cast<const acc_t*>(a.inv_norm);
+  const acc_t* h_g = reinterpret_cast<const acc_t*>(a.hterm);
+  acc_t* state = reinterpret_cast<acc_t*>(a.state);
+  acc_t* traj = reinterpret_cast<acc_t*>(a.traj);
+  const acc_t coef_t = reinterpret_cast<const acc_t*>(a.coef)[t - 1];
+  acc_t inv[4], hv[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    inv[v] = inv_g[row0 + v];
+    hv[v] = h_g[row0 + v];
+  }
+  const int k_rec = t - a.t_begin;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int r = rbase + ct * 16 + c;
+    const bool live_r = r < a.R;
+    acc_t s[4], fld[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      fld[v] = acc[ct][v];
+      s[v] = (live_r && row0 + v < N) ? state[(size_t)r * N + row0 + v] : (acc_t)0;
+    }
+    Epilogue<P>::apply(fld, inv, hv, s, a, coef_t, (uint32_t)(row0 >> 2), (uint32_t)r, (uint32_t)t);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (row0 + v >= N || !live_r) s[v] = (acc_t)0;
+    op_t* dst = S_next + (size_t)r * Kp + row0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[v] = (op_t)s[v];
+    if (live_r) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (row0 + v < N) {
+          state[(size_t)r * N + row0 + v] = s[v];
+          if (traj && k_rec < a.record) traj[((size_t)k_rec * a.R + r) * N + row0 + v] = s[v];
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Operand copy of a master state: S[r][i] = (op_t) state[r][i] for i < N, r < R; zero padding.
+// ------------------------------------------------------------------------------------------
+template <typename op_t, typename acc_t>
+__global__ void pack_state_kernel(const acc_t* __restrict__ state, op_t* __restrict__ S, int N, int R,
+                                  int Kp, int Rp, int zero) {
+  const size_t total = (size_t)Rp * Kp;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / Kp);
+    const int i = (int)(idx - (size_t)r * Kp);
+    acc_t v = 0;
+    if (!zero && r < R && i < N) v = state[(size_t)r * N + i];
+    S[idx] = (op_t)v;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Readout: s~ = +1 if s >= 0 (including -0.0), else -1.
+// ------------------------------------------------------------------------------------------
+template <typename acc_t>
+__global__ void readout_kernel(const acc_t* __restrict__ state, int8_t* __restrict__ spins, size_t count) {
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
+       idx += (size_t)gridDim.x * blockDim.x)
+    spins[idx] = (state[idx] >= (acc_t)0) ? (int8_t)1 : (int8_t)-1;
+}
+
+// ------------------------------------------------------------------------------------------
+// Energy of Eq. 1 (pairs i < j) for R spin vectors, E = (1/2) sum_i s_i y_i + sum_i h_i s_i with
+// y_i = sum_j J_ij s_j. Integral J (int8): y and the pair term are exact int32/int64. Block =
+// 256 threads handles one replica; thread i accumulates y_i by reading J column i (= row i by
+// symmetry, so consecutive threads read consecutive bytes), then the products s_i y_i are
+// reduced with wavefront shuffles and one LDS step. The field term uses integer h when h is
+// integral; otherwise lane 0 sums h_i s_i in double in ascending i.
+// FP64 J (non-integral couplings): y_i in double, reduced in a fixed tree order.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void energy_kernel(const int8_t* __restrict__ J8,
+                                                     const double* __restrict__ J64,
+                                                     const double* __restrict__ h,
+                                                     int h_integral,
+                                                     const int8_t* __restrict__ spins, int N, int R,
+                                                     long long* __restrict__ E_int,
+                                                     double* __restrict__ E) {
+  __shared__ int8_t s_sh[8192];
+  __shared__ long long part_i[4];
+  __shared__ double part_d[4];
+  const int r = blockIdx.x;
+  if (r >= R) return;
+  const int8_t* s = spins + (size_t)r * N;
+  // spins of this replica in LDS, in chunks of 8192
+  long long pair2 = 0;   // sum_i s_i y_i (integral J)
+  double pair2_d = 0.0;  // same, FP64 J
+  long long fld_i = 0;
+  for (int base = 0; base < N; base += 8192) {
+    const int len = min(8192, N - base);
+    __syncthreads();
+    for (int k = threadIdx.x; k < len; k += blockDim.x) s_sh[k] = s[base + k];
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      if (J8) {
+        int y = 0;
+        const int8_t* col = J8 + (size_t)base * N + i;
+        for (int j = 0; j < len; ++j) y += (int)col[(size_t)j * N] * (int)s_sh[j];
+        pair2 += (long long)y * (long long)s[i];
+      } else {
+        double y = 0.0;
+        const double* col = J64 + (size_t)base * N + i;
+        for (int j = 0; j < len; ++j) y += col[(size_t)j * N] * (double)s_sh[j];
+        pair2_d += y * (double)s[i];
+      }
+    }
+  }
+  if (h && h_integral) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) fld_i += (long long)h[i] * (long long)s[i];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  long long v = wave_sum_i64(pair2 + 2 * fld_i);
+  double vd = wave_sum_f64(pair2_d);
+  if (lane == 0) {
+    part_i[wave] = v;
+    part_d[wave] = vd;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    double totd = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      tot += part_i[w];
+      totd += part_d[w];
+    }
+    if (J8) {
+      const long long e2 = tot;  // 2 * (pair + integral field)
+      double field_real = 0.0;
+      if (h && !h_integral) {
+        for (int i = 0; i < N; ++i) field_real += h[i] * (double)s[i];
+      }
+      if (E_int) E_int[r] = e2 / 2;
+      E[r] = (h && !h_integral) ? (double)(e2 / 2) + field_real : (double)(e2 / 2);
+    } else {
+      double field = 0.0;
+      if (h) {
+        for (int i = 0; i < N; ++i) field += h[i] * (double)s[i];
+      }
+      if (E_int) E_int[r] = 0;
+      E[r] = 0.5 * totd + field;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Noise words / values for a range of spins (library utility and test hook for the stream).
+// words: out[(k*n + i)] for replica r0 + k ... see nmfa.h.
+// ------------------------------------------------------------------------------------------
+__global__ void noise_words_kernel(uint32_t key0, uint32_t key1, uint32_t t, uint32_t r0, int nrep,
+                                   int nq, uint32_t* out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nrep * nq) return;
+  const int k = idx / nq, q = idx - k * nq;
+  const Philox4 w = philox4x32_10((uint32_t)q, r0 + (uint32_t)k, t, 0u, key0, key1);
+  out[4 * (size_t)idx + 0] = w.x0;
+  out[4 * (size_t)idx + 1] = w.x1;
+  out[4 * (size_t)idx + 2] = w.x2;
+  out[4 * (size_t)idx + 3] = w.x3;
+}
+
+__global__ void noise_values_kernel(uint32_t key0, uint32_t key1, uint32_t t, uint32_t r0, int nrep,
+                                    int nq, int fp64, double* out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nrep * nq) return;
+  const int k = idx / nq, q = idx - k * nq;
+  const Philox4 w = philox4x32_10((uint32_t)q, r0 + (uint32_t)k, t, 0u, key0, key1);
+  if (fp64) {
+    double z[4];
+    gauss4_f64(w, z);
+    for (int v = 0; v < 4; ++v) out[4 * (size_t)idx + v] = z[v];
+  } else {
+    float z[4];
+    // sigma = 1: -2 ln 2 * 1
+    sigma_gauss4_f32(w, -2.0f * 0.6931471805599453f, z);
+    for (int v = 0; v < 4; ++v) out[4 * (size_t)idx + v] = (double)z[v];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host-side launchers.
+// ------------------------------------------------------------------------------------------
+template <int P, bool J8>
+static hipError_t launch_small_t(const AnnealArgs& a, hipStream_t st) {
+  const int waves = a.Mp / 16;
+  const size_t es = (P == PREC_FP64) ? 8 : (P == PREC_FP32 ? 4 : 2);
+  const size_t lds = ((size_t)a.Mp + 32) * a.lds_stride * es;
+  hipError_t e = hipFuncSetAttribute((const void*)anneal_small<P, J8>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int blocks = (a.R + 15) / 16;
+  hipLaunchKernelGGL((anneal_small<P, J8>), dim3(blocks), dim3(64 * waves), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_anneal_small(int prec, const AnnealArgs& a, hipStream_t st) {
+  switch (prec) {
+    case PREC_FP64: return launch_small_t<PREC_FP64, false>(a, st);
+    case PREC_FP32: return launch_small_t<PREC_FP32, false>(a, st);
+    case PREC_BF16: return launch_small_t<PREC_BF16, false>(a, st);
+    case PREC_FP8J_BF16S: return launch_small_t<PREC_BF16, true>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+size_t small_lds_bytes(int prec, int Mp, int stride) {
+  const size_t es = (prec == PREC_FP64) ? 8 : (prec == PREC_FP32 ? 4 : 2);
+  return ((size_t)Mp + 32) * stride * es;
+}
+
+hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
+                              hipStream_t st) {
+  const dim3 grid(a.Mp / 64, a.Rp / 64);
+  switch (prec) {
+    case PREC_FP64:
+      hipLaunchKernelGGL((anneal_step<PREC_FP64>), grid, dim3(256), 0, st, a, S_cur, S_next, t);
+      break;
+    case PREC_FP32:
+      hipLaunchKernelGGL((anneal_step<PREC_FP32>), grid, dim3(256), 0, st, a, S_cur, S_next, t);
+      break;
+    case PREC_BF16:
+    case PREC_FP8J_BF16S:
+      hipLaunchKernelGGL((anneal_step<PREC_BF16>), grid, dim3(256), 0, st, a, S_cur, S_next, t);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R, int Kp, int Rp, int zero,
+                             hipStream_t st) {
+  const size_t total = (size_t)Rp * Kp;
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 4096);
+  switch (prec) {
+    case PREC_FP64:
+      hipLaunchKernelGGL((pack_state_kernel<double, double>), dim3(blocks), dim3(256), 0, st,
+                         (const double*)state, (double*)S, N, R, Kp, Rp, zero);
+      break;
+    case PREC_FP32:
+      hipLaunchKernelGGL((pack_state_kernel<float, float>), dim3(blocks), dim3(256), 0, st,
+                         (const float*)state, (float*)S, N, R, Kp, Rp, zero);
+      break;
+    default:
+      hipLaunchKernelGGL((pack_state_kernel<__bf16, float>), dim3(blocks), dim3(256), 0, st,
+                         (const float*)state, (__bf16*)S, N, R, Kp, Rp, zero);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_readout(int prec, const void* state, int8_t* spins, size_t count, hipStream_t st) {
+  const int blocks = (int)std::min<size_t>((count + 255) / 256, 8192);
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL((readout_kernel<double>), dim3(blocks), dim3(256), 0, st, (const double*)state,
+                       spins, count);
+  else
+    hipLaunchKernelGGL((readout_kernel<float>), dim3(blocks), dim3(256), 0, st, (const float*)state,
+                       spins, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const int8_t* J8, const double* J64, const double* h, int h_integral,
+                         const int8_t* spins, int N, int R, long long* E_int, double* E, hipStream_t st) {
+  hipLaunchKernelGGL(energy_kernel, dim3(R), dim3(256), 0, st, J8, J64, h, h_integral, spins, N, R,
+                     E_int, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise_words(uint32_t k0, uint32_t k1, uint32_t t, uint32_t r0, int nrep, int nq,
+                              uint32_t* out, hipStream_t st) {
+  const int total = nrep * nq;
+  hipLaunchKernelGGL(noise_words_kernel, dim3((total + 255) / 256), dim3(256), 0, st, k0, k1, t, r0, nrep,
+                     nq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise_values(uint32_t k0, uint32_t k1, uint32_t t, uint32_t r0, int nrep, int nq,
+                               int fp64, double* out, hipStream_t st) {
+  const int total = nrep * nq;
+  hipLaunchKernelGGL(noise_values_kernel, dim3((total + 255) / 256), dim3(256), 0, st, k0, k1, t, r0,
+                     nrep, nq, fp64, out);
+  return hipGetLastError();
+}
+
+}  // namespace nmfa

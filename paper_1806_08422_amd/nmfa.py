@@ -1,0 +1,255 @@
+"""Thin Python binding of libnmfa.so (the C ABI declared in include/nmfa.h).
+
+Argument marshalling only: every step of the annealing runs in the library's HIP kernels. The
+library must have been built (``python -m paper_1806_08422_amd.build``); if it is missing or
+cannot be loaded, importing this module raises -- there is no CPU fallback.
+
+PyTorch, when present, is used only to pick up the current HIP stream (``stream=None``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnmfa.so")
+
+NMFA_OK = 0
+NMFA_EINVAL = -1
+NMFA_ENOMEM = -2
+NMFA_EDEVICE = -3
+NMFA_ESTATE = -4
+NMFA_ECANCELED = -5
+
+FP64, FP32, BF16, FP8J_BF16S = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp8j_bf16s": FP8J_BF16S}
+
+FLAG_NEGATE_NOISE = 0x1
+FLAG_UPPER_TRIANGULAR = 0x2
+FLAG_FORCE_STEP = 0x4
+
+# Every function declared in include/nmfa.h (checked by the CPU tests against the header).
+EXPORTS = (
+    "nmfa_params_default", "nmfa_create", "nmfa_anneal", "nmfa_anneal_range", "nmfa_spins",
+    "nmfa_energies", "nmfa_cuts", "nmfa_energies_of", "nmfa_get_state", "nmfa_set_state",
+    "nmfa_trajectory", "nmfa_info", "nmfa_last_timing", "nmfa_destroy", "nmfa_noise_words",
+    "nmfa_noise_values", "nmfa_last_error",
+)
+
+
+class NmfaError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"[{code}] {message}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("precision", ctypes.c_uint32),
+        ("alpha", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("n_knots", ctypes.c_int32),
+        ("knot_u", ctypes.POINTER(ctypes.c_double)),
+        ("knot_T", ctypes.POINTER(ctypes.c_double)),
+        ("flags", ctypes.c_uint32),
+        ("record_iters", ctypes.c_int32),
+    ]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first (python -m paper_1806_08422_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32, u64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "nmfa_params_default": ([ctypes.POINTER(Params)], None),
+        "nmfa_create": ([i32, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(vp)], ctypes.c_int),
+        "nmfa_anneal": ([vp, i32, i32, u64, vp], ctypes.c_int),
+        "nmfa_anneal_range": ([vp, i32, i32, i32, i32, u64, vp], ctypes.c_int),
+        "nmfa_spins": ([vp, vp, i32], ctypes.c_int),
+        "nmfa_energies": ([vp, vp, vp], ctypes.c_int),
+        "nmfa_cuts": ([vp, vp], ctypes.c_int),
+        "nmfa_energies_of": ([vp, i32, vp, vp, vp], ctypes.c_int),
+        "nmfa_get_state": ([vp, vp], ctypes.c_int),
+        "nmfa_set_state": ([vp, i32, vp], ctypes.c_int),
+        "nmfa_trajectory": ([vp, vp], ctypes.c_int),
+        "nmfa_info": ([vp, vp, vp, vp], ctypes.c_int),
+        "nmfa_last_timing": ([vp, vp, vp, vp], ctypes.c_int),
+        "nmfa_destroy": ([vp], None),
+        "nmfa_noise_words": ([u64, i32, i32, i32, i32, vp], ctypes.c_int),
+        "nmfa_noise_values": ([u64, i32, i32, i32, i32, i32, vp], ctypes.c_int),
+        "nmfa_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int) -> None:
+    if rc != NMFA_OK:
+        raise NmfaError(rc, lib.nmfa_last_error().decode(errors="replace"))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def current_stream_handle() -> Optional[int]:
+    """The raw hipStream_t of torch's current stream, or None (the null stream)."""
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class Solver:
+    """One Ising instance (h, J) prepared on the current GPU; see nmfa_create in include/nmfa.h."""
+
+    def __init__(self, J: np.ndarray, h: Optional[np.ndarray] = None, precision="bf16",
+                 alpha: float = 0.15, sigma: float = 0.15,
+                 knots: Optional[Sequence[Tuple[float, float]]] = None, record_iters: int = 0,
+                 negate_noise: bool = False, upper_triangular: bool = False,
+                 force_step: bool = False):
+        J = np.ascontiguousarray(J, dtype=np.float64)
+        if J.ndim != 2 or J.shape[0] != J.shape[1]:
+            raise ValueError("J must be a square matrix")
+        self.n = int(J.shape[0])
+        hh = None if h is None else np.ascontiguousarray(h, dtype=np.float64)
+        p = Params()
+        lib.nmfa_params_default(ctypes.byref(p))
+        p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        p.alpha = float(alpha)
+        p.sigma = float(sigma)
+        p.record_iters = int(record_iters)
+        flags = 0
+        if negate_noise:
+            flags |= FLAG_NEGATE_NOISE
+        if upper_triangular:
+            flags |= FLAG_UPPER_TRIANGULAR
+        if force_step:
+            flags |= FLAG_FORCE_STEP
+        p.flags = flags
+        if knots is not None:
+            ku = np.ascontiguousarray([k[0] for k in knots], dtype=np.float64)
+            kT = np.ascontiguousarray([k[1] for k in knots], dtype=np.float64)
+            p.n_knots = len(knots)
+            p.knot_u = ku.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            p.knot_T = kT.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        handle = ctypes.c_void_p()
+        _check(lib.nmfa_create(self.n, _ptr(J), _ptr(hh), ctypes.byref(p), ctypes.byref(handle)))
+        self._h = handle
+        self.R = 0
+        self.record_iters = int(record_iters)
+        self._iters_last = 0
+
+    # -- lifecycle ---------------------------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.nmfa_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- annealing ----------------------------------------------------------------------------
+    def anneal(self, R: int, t_f: int, seed: int, stream: Optional[int] = None) -> None:
+        self.anneal_range(R, t_f, 1, t_f, seed, stream)
+
+    def anneal_range(self, R: int, t_f: int, t_begin: int, t_end: int, seed: int,
+                     stream: Optional[int] = None) -> None:
+        st = current_stream_handle() if stream is None else stream
+        _check(lib.nmfa_anneal_range(self._h, int(R), int(t_f), int(t_begin), int(t_end),
+                                     int(seed) & (2**64 - 1), st))
+        self.R = int(R)
+        self._iters_last = int(t_end) - int(t_begin) + 1
+
+    # -- results ------------------------------------------------------------------------------
+    def spins(self) -> np.ndarray:
+        out = np.zeros((self.R, self.n), dtype=np.int8)
+        _check(lib.nmfa_spins(self._h, _ptr(out), 0))
+        return out
+
+    def spins_to_device(self, device_ptr: int) -> None:
+        _check(lib.nmfa_spins(self._h, ctypes.c_void_p(device_ptr), 1))
+
+    def energies(self) -> Tuple[np.ndarray, np.ndarray]:
+        E = np.zeros(self.R)
+        Ei = np.zeros(self.R, dtype=np.int64)
+        _check(lib.nmfa_energies(self._h, _ptr(E), _ptr(Ei)))
+        return E, Ei
+
+    def cuts(self) -> np.ndarray:
+        out = np.zeros(self.R)
+        _check(lib.nmfa_cuts(self._h, _ptr(out)))
+        return out
+
+    def energies_of(self, spins: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+        s = np.ascontiguousarray(spins, dtype=np.int8)
+        R = int(s.shape[0])
+        E = np.zeros(R)
+        Ei = np.zeros(R, dtype=np.int64)
+        _check(lib.nmfa_energies_of(self._h, R, _ptr(s), _ptr(E), _ptr(Ei)))
+        return E, Ei
+
+    def state(self) -> np.ndarray:
+        out = np.zeros((self.R, self.n))
+        _check(lib.nmfa_get_state(self._h, _ptr(out)))
+        return out
+
+    def set_state(self, s: np.ndarray) -> None:
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        _check(lib.nmfa_set_state(self._h, int(s.shape[0]), _ptr(s)))
+        self.R = int(s.shape[0])
+
+    def trajectory(self) -> np.ndarray:
+        k = min(self.record_iters, self._iters_last)
+        out = np.zeros((k, self.R, self.n))
+        _check(lib.nmfa_trajectory(self._h, _ptr(out)))
+        return out
+
+    def info(self) -> dict:
+        n, p, path = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.nmfa_info(self._h, ctypes.byref(n), ctypes.byref(p), ctypes.byref(path)))
+        return {"n": n.value, "precision": p.value, "path": ("persistent", "step")[path.value]}
+
+    def last_timing(self) -> dict:
+        a, t, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _check(lib.nmfa_last_timing(self._h, ctypes.byref(a), ctypes.byref(t), ctypes.byref(n)))
+        return {"anneal_ms": float(a.value), "total_ms": float(t.value), "launches": int(n.value)}
+
+
+def noise_words(seed: int, t: int, r0: int, n_rep: int, n_quads: int) -> np.ndarray:
+    out = np.zeros((n_rep, n_quads, 4), dtype=np.uint32)
+    _check(lib.nmfa_noise_words(int(seed), int(t), int(r0), int(n_rep), int(n_quads), _ptr(out)))
+    return out
+
+
+def noise_values(seed: int, t: int, r0: int, n_rep: int, n_quads: int, fp64: bool) -> np.ndarray:
+    """Standard normal numbers z(t, r0+k, 4q+w) as [n_rep, 4*n_quads] (spin index last)."""
+    out = np.zeros((n_rep, n_quads * 4))
+    _check(lib.nmfa_noise_values(int(seed), int(t), int(r0), int(n_rep), int(n_quads),
+                                 int(bool(fp64)), _ptr(out)))
+    return out

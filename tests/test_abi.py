@@ -1,0 +1,69 @@
+"""The C-ABI library loads and exports every function that include/*.h declares; host-side
+argument validation rejects bad inputs before touching the GPU (no GPU needed)."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(hdr).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(nmfa_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for must in ("nmfa_create", "nmfa_anneal", "nmfa_energies", "nmfa_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1806_08422_amd import nmfa
+
+    lib = ctypes.CDLL(nmfa.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(nmfa.EXPORTS) <= set(_declared())
+
+
+def _create_rc(J, h=None, **kw):
+    from paper_1806_08422_amd import nmfa
+
+    with pytest.raises(nmfa.NmfaError) as ei:
+        nmfa.Solver(J, h, **kw)
+    return ei.value.code, str(ei.value)
+
+
+def test_rejects_asymmetric_couplings():
+    J = np.array([[0.0, 1.0], [2.0, 0.0]])
+    code, msg = _create_rc(J)
+    assert code == -1 and "symmetric" in msg
+
+
+def test_rejects_diagonal_and_nan():
+    assert _create_rc(np.eye(3))[0] == -1
+    J = np.zeros((3, 3))
+    J[0, 1] = J[1, 0] = np.nan
+    assert _create_rc(J)[0] == -1
+    assert _create_rc(np.zeros((3, 3)), np.array([0.0, np.inf, 0.0]))[0] == -1
+
+
+def test_rejects_bad_parameters_and_schedules():
+    J = np.zeros((4, 4))
+    assert _create_rc(J, alpha=0.0)[0] == -1
+    assert _create_rc(J, alpha=1.5)[0] == -1
+    assert _create_rc(J, sigma=-0.1)[0] == -1
+    assert _create_rc(J, knots=[(0.0, 1.0), (1.0, -2.0)])[0] == -1
+    assert _create_rc(J, knots=[(0.0, 1.0), (0.5, 0.5), (0.4, 0.2), (1.0, 0.1)])[0] == -1
+    assert _create_rc(J, knots=[(0.1, 1.0), (1.0, 0.5)])[0] == -1
+    assert _create_rc(J, precision=7)[0] == -1
