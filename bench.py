@@ -56,11 +56,18 @@ def timed_anneals(solver, R, t_f, seeds, stream):
     return walls, timings
 
 
-def cpu_baseline(inst, t_f_full: int, R_sample: int, iters: int):
+def cpu_baseline(inst, t_f_full: int, R_sample: int, target_s: float):
+    """The CPU oracle on a bounded sample of the same workload: R_sample replicas for the first
+    iterations of the schedule, sized from a short calibration run to about target_s seconds."""
     import oracle
 
-    T = oracle.schedule(t_f_full)[:iters]
     threads = oracle.num_threads()
+    T_full = oracle.schedule(t_f_full)
+    t0 = time.perf_counter()
+    oracle.anneal(inst.J, inst.h, T_full[:4], R=R_sample, seed=2024, threads=threads)
+    per_iter = (time.perf_counter() - t0) / 4
+    iters = int(min(t_f_full, max(4, target_s / max(per_iter, 1e-6))))
+    T = T_full[:iters]
     t0 = time.perf_counter()
     oracle.anneal(inst.J, inst.h, T, R=R_sample, seed=2024, threads=threads)
     dt = time.perf_counter() - t0
@@ -74,6 +81,81 @@ def cpu_baseline(inst, t_f_full: int, R_sample: int, iters: int):
     }
 
 
+class _InstanceCache:
+    """Instances for the serving stream. Dense SK requests use principal submatrices of one
+    SK(2000) instance (a principal submatrix of an SK instance is an SK instance); sparse requests
+    use random d-regular graphs cached per (N rounded to 100, d)."""
+
+    def __init__(self, instances_mod):
+        self.inst = instances_mod
+        self.sk_big = instances_mod.sk(2000, 424242).J
+        self.reg = {}
+
+    def get(self, job):
+        if job.kind == "sk":
+            J = self.sk_big[: job.n, : job.n]
+        else:
+            n = max(100, int(round(job.n / 100.0)) * 100)
+            key = (n, job.degree)
+            if key not in self.reg:
+                self.reg[key] = self.inst.random_regular(n, job.degree, 1000 + n + job.degree).J
+            J = self.reg[key]
+        h = self.inst.gaussian_fields(J.shape[0], 0.5, job.instance_seed) if job.with_fields else None
+        return J, h
+
+
+def serving_leg(nmfa, instances_mod, n_burst: int, n_stream: int, budget_bytes: int, seed: int = 5):
+    """Continuous-batching server: saturation throughput from a burst, then p50/p99 solve latency
+    of a Poisson stream at 80% of that rate."""
+    cache = _InstanceCache(instances_mod)
+    burst = instances_mod.serving_stream(n_burst, 0.0, seed)
+    for j in burst:
+        cache.get(j)
+    out = {}
+    with nmfa.Server(precision="bf16", hbm_budget_bytes=budget_bytes, max_active=256, chunk_iters=250) as srv:
+        t0 = time.perf_counter()
+        tickets = []
+        work = 0
+        for j in burst:
+            J, h = cache.get(j)
+            tickets.append(srv.submit(J, h, j.R, j.t_f, j.noise_seed))
+            work += J.shape[0] * j.R * j.t_f
+        for t in tickets:
+            srv.wait(t)
+        dt = time.perf_counter() - t0
+        for t in tickets:
+            srv.release(t)
+        rate = n_burst / dt
+        out["burst"] = {"requests": n_burst, "seconds": dt, "requests_per_s": rate,
+                        "spin_updates_per_s": work / dt, "stats": srv.stats()}
+        lam = 0.8 * rate
+        stream = instances_mod.serving_stream(n_stream, lam, seed + 1)
+        for j in stream:
+            cache.get(j)
+        lat = []
+        pending = []
+        start = time.perf_counter()
+        work = 0
+        for j in stream:
+            delay = start + j.arrival_s - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            J, h = cache.get(j)
+            pending.append(srv.submit(J, h, j.R, j.t_f, j.noise_seed))
+            work += J.shape[0] * j.R * j.t_f
+        for t in pending:
+            srv.wait(t)
+            lat.append(srv.result(t)["latency_ms"])
+            srv.release(t)
+        dt = time.perf_counter() - start
+        lat = np.array(lat)
+        out["poisson"] = {"requests": n_stream, "rate_per_s": lam, "seconds": dt,
+                          "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                          "mean_ms": float(lat.mean()), "spin_updates_per_s": work / dt,
+                          "stats": srv.stats(), "budget_bytes": budget_bytes}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,7 +163,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP64 and N=100 side runs")
-    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-burst", type=int, default=200)
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--serving-budget-gib", type=float, default=2.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the replica-sharded multi-GPU path is "
@@ -211,8 +297,13 @@ def main() -> int:
         }
         result["extra"] = extra
 
+    if not args.no_serving:
+        result.setdefault("extra", {})["serving"] = serving_leg(
+            nmfa, instances, args.serving_burst, args.serving_requests,
+            int(args.serving_budget_gib * (1 << 30)))
+
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(inst, T_F, R_sample=16, iters=args.cpu_iters)
+        result["cpu_baseline"] = cpu_baseline(inst, T_F, R_sample=16, target_s=args.cpu_seconds)
     solver.close()
     print(json.dumps(result), flush=True)
     return 0

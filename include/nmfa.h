@@ -70,6 +70,8 @@ typedef enum nmfa_precision {
 #define NMFA_FLAG_NEGATE_NOISE 0x1u   /* test hook: use -z for every Gaussian z */
 #define NMFA_FLAG_UPPER_TRIANGULAR 0x2u /* J holds only i<j; the library mirrors it */
 #define NMFA_FLAG_FORCE_STEP 0x4u     /* use the per-iteration (large-N) kernel even if N is small */
+#define NMFA_FLAG_FORCE_XCD 0x8u      /* use the persistent XCD-group kernel (BF16 / FP8-J only) */
+#define NMFA_FLAG_FORCE_FENCED 0x10u  /* XCD-group kernel: exchange with device-scope fences */
 
 /* ---- parameters ------------------------------------------------------------------------------
  * Fill with nmfa_params_default() and override fields. struct_size must be sizeof(nmfa_params)
@@ -146,8 +148,11 @@ int nmfa_set_state(nmfa_ctx *c, int32_t R, const double *in);
  * k < min(record_iters, iterations run) (host, doubles). Errors: ESTATE, EDEVICE. */
 int nmfa_trajectory(nmfa_ctx *c, double *out);
 
-/* Information about a context: writes n, the precision and the kernel path the last anneal used
- * (0 = persistent small-N kernel, 1 = per-iteration kernel). Errors: EINVAL. */
+/* Information about a context: writes n, the precision and the kernel path (0 = persistent
+ * small-N kernel with J in LDS; 1 = per-iteration kernel; 2 = persistent XCD-group kernel whose
+ * groups exchanged spins through one XCD's L2; 3 = the same kernel with device-scope fences,
+ * used when a group's workgroups were not all placed on one XCD). Paths 2/3 are only told
+ * apart after an anneal has completed (the call synchronises). Errors: EINVAL, EDEVICE. */
 int nmfa_info(nmfa_ctx *c, int32_t *n, int32_t *precision, int32_t *path);
 
 /* Device time of the last anneal in milliseconds, from HIP events recorded on the anneal's own
@@ -172,6 +177,80 @@ int nmfa_noise_values(uint64_t seed, int32_t t, int32_t r0, int32_t n_rep, int32
 
 /* Human-readable message of the last failing call on this thread ("" if none). */
 const char *nmfa_last_error(void);
+
+/* ---- serving: continuous batching of annealing requests ---------------------------------------
+ * A server owns one GPU stream and a scheduler thread. Requests (instance, R, t_f, seed) are
+ * admitted in arrival order while the device memory they need fits in hbm_budget_bytes and fewer
+ * than max_active are running; a request that does not fit waits (later requests do not overtake
+ * it), one larger than the whole budget fails with NMFA_ENOMEM. Admitted requests are advanced in
+ * rounds of chunk_iters iterations: every round runs one batched launch of the persistent small-N
+ * kernel over the replica blocks of all admitted small-N requests, plus the large-N requests'
+ * own kernels, so requests that arrive while others run join at the next round and their work
+ * overlaps on the device. J and the spin state stay on the device between rounds. Because the
+ * noise is counter-based and every request's arithmetic depends only on that request, a
+ * request's result is bit-identical alone and in any mix. The scheduler runs the paper's
+ * Algorithm 1 per request exactly as nmfa_anneal does (same kernels, same precision). */
+typedef struct nmfa_server nmfa_server;
+
+typedef struct nmfa_server_params {
+  uint32_t struct_size;       /* sizeof(nmfa_server_params) */
+  uint32_t precision;         /* nmfa_precision of every request; default NMFA_BF16 */
+  uint64_t hbm_budget_bytes;  /* device memory the admitted requests may hold; default 8 GiB */
+  int32_t max_active;         /* admitted requests at once; default 256 */
+  int32_t chunk_iters;        /* iterations per scheduling round; default 250 */
+} nmfa_server_params;
+
+typedef struct nmfa_server_stats {
+  uint64_t submitted, completed, failed, cancelled;
+  uint64_t queued, active;            /* at the time of the call */
+  uint64_t bytes_in_use, peak_bytes;  /* admitted device bytes (the budget's accounting) */
+  uint64_t rounds, batched_launches;
+} nmfa_server_stats;
+
+/* Request states reported by nmfa_server_poll. */
+#define NMFA_JOB_QUEUED 0
+#define NMFA_JOB_RUNNING 1
+#define NMFA_JOB_DONE 2
+
+void nmfa_server_params_default(nmfa_server_params *p);
+
+/* Start a server on the current HIP device. Errors: EINVAL, ENOMEM, EDEVICE. */
+int nmfa_server_create(const nmfa_server_params *p, nmfa_server **out);
+
+/* Queue a request: n spins, J (host, n*n, symmetric, zero diagonal), h (host, n, or NULL),
+ * R replicas, t_f iterations, noise seed. The library copies J and h before returning; the
+ * instance is validated when the request is admitted (a bad instance fails the request).
+ * *ticket identifies the request. Errors: EINVAL (sizes), ESTATE (server stopping). */
+int nmfa_server_submit(nmfa_server *s, int32_t n, const double *J, const double *h, int32_t R, int32_t t_f,
+                       uint64_t seed, uint64_t *ticket);
+
+/* *status = NMFA_JOB_QUEUED / RUNNING / DONE, or the negative error code of a failed or
+ * cancelled (NMFA_ECANCELED) request. Errors: EINVAL (unknown ticket). */
+int nmfa_server_poll(nmfa_server *s, uint64_t ticket, int32_t *status);
+
+/* Block until the request has finished (done, failed or cancelled) or timeout_ms elapsed
+ * (negative: no limit). Returns NMFA_OK when it finished, NMFA_ESTATE on timeout. */
+int nmfa_server_wait(nmfa_server *s, uint64_t ticket, int32_t timeout_ms);
+
+/* Results of a finished request: E (R doubles), E_int (R int64, or NULL; 0 unless J and h are
+ * integral), spins (R*n int8, or NULL), latency_ms (submit to results on the host, or NULL).
+ * Errors: EINVAL (unknown ticket), ESTATE (not done), or the request's own failure code. */
+int nmfa_server_result(nmfa_server *s, uint64_t ticket, double *E, int64_t *E_int, int8_t *spins,
+                       double *latency_ms);
+
+/* Forget a finished request and free its host-side results. Errors: EINVAL, ESTATE (not finished). */
+int nmfa_server_release(nmfa_server *s, uint64_t ticket);
+
+/* Cancel a request: a queued one is dropped at once, a running one at the next round boundary.
+ * Errors: EINVAL (unknown ticket), ESTATE (already finished). */
+int nmfa_server_cancel(nmfa_server *s, uint64_t ticket);
+
+/* Counters of the server. Errors: EINVAL. */
+int nmfa_server_stats_get(nmfa_server *s, nmfa_server_stats *out);
+
+/* Cancel whatever is queued, let running requests stop at the next round, join the scheduler
+ * and free everything (NULL is ignored). */
+void nmfa_server_destroy(nmfa_server *s);
 
 #ifdef __cplusplus
 }

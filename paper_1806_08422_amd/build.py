@@ -13,8 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnmfa.so")
-HIP_SOURCES = ["nmfa_kernels.hip"]
-CXX_SOURCES = ["nmfa_api.cpp"]
+HIP_SOURCES = ["nmfa_kernels.hip", "nmfa_xcd.hip"]
+CXX_SOURCES = ["nmfa_api.cpp", "nmfa_server.cpp"]
 
 ARCH = os.environ.get("NMFA_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
@@ -50,7 +50,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/nmfa.h"
+#include "nmfa_ctx.h"
 #include "nmfa_internal.h"
 
 using namespace nmfa;
@@ -21,7 +22,7 @@ using namespace nmfa;
 // ------------------------------------------------------------------------------------------
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char* fmt, ...) {
+int nmfa_fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -30,6 +31,7 @@ static int fail(int code, const char* fmt, ...) {
   g_last_error = buf;
   return code;
 }
+#define fail nmfa_fail
 
 #define HIP_TRY(expr)                                                                       \
   do {                                                                                      \
@@ -99,54 +101,6 @@ static bool is_integral(double v) { return std::isfinite(v) && v == std::floor(v
 // ------------------------------------------------------------------------------------------
 // Context
 // ------------------------------------------------------------------------------------------
-struct nmfa_ctx {
-  int n = 0;
-  int prec = NMFA_BF16;
-  int path = 0;  // 0 = persistent small-N kernel, 1 = per-iteration kernel
-  int Mp = 0, Kp = 0, lds_stride = 0;
-  double alpha = 0.15, sigma = 0.15;
-  uint32_t flags = 0;
-  int record = 0;
-  std::vector<double> ku, kT;
-  std::vector<double> h;  // empty if h = 0
-  bool has_h = false;
-  bool J_integral = false, h_integral = true;
-  double w_total = 0.0;  // sum_{i<j} J_ij
-  int device = 0;
-
-  // device data of the instance
-  void* d_J = nullptr;       // operand layout of the selected path
-  void* d_inv = nullptr;     // [Mp] acc_t
-  void* d_hterm = nullptr;   // [Mp] acc_t
-  int8_t* d_J8 = nullptr;    // [n][n] for exact energies (integral |J| <= 127)
-  double* d_J64 = nullptr;   // [n][n] otherwise
-  double* d_h = nullptr;     // [n] or null
-
-  // per-run buffers
-  int cap_R = 0;             // replicas the buffers hold
-  int R = 0, t_f = 0;        // current run
-  uint64_t seed = 0;
-  bool state_valid = false;
-  bool result_valid = false;
-  int traj_iters = 0;        // iterations recorded by the last call
-  void* d_state = nullptr;   // [R][n] acc_t
-  int8_t* d_spins = nullptr; // [R][n]
-  double* d_E = nullptr;     // [R]
-  long long* d_Eint = nullptr;
-  void* d_S[2] = {nullptr, nullptr};  // per-iteration path: [Rp][Kp] op_t
-  int cap_Rp = 0;
-  void* d_traj = nullptr;
-  size_t traj_cap = 0;
-  void* d_coef = nullptr;
-  int coef_tf = 0;
-  hipStream_t stream = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
-  int launches = 0;
-  bool timed = false;
-
-  size_t acc_size() const { return prec == NMFA_FP64 ? 8 : 4; }
-  size_t op_size() const { return prec == NMFA_FP64 ? 8 : (prec == NMFA_FP32 ? 4 : 2); }
-};
 
 static void free_run_buffers(nmfa_ctx* c) {
   (void)hipFree(c->d_state);
@@ -192,6 +146,7 @@ extern "C" void nmfa_destroy(nmfa_ctx* c) {
   (void)hipFree(c->d_h);
   (void)hipFree(c->d_traj);
   (void)hipFree(c->d_coef);
+  (void)hipFree(c->d_ctl);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->evm) (void)hipEventDestroy(c->evm);
@@ -300,17 +255,47 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   // kernel path and padded layout
   const size_t es = c->op_size();
   const bool bf = (c->prec == NMFA_BF16 || c->prec == NMFA_FP8J_BF16S);
+  bool j_fp8_exact = true;  // every coupling is exactly an FP8 E4M3 value
+  for (size_t k = 0; k < nn && j_fp8_exact; ++k) {
+    const uint8_t b = fp8e4m3_bits(Jf[k]);
+    const int e = (b >> 3) & 0xf, m = b & 7;
+    double w = (e == 0) ? std::ldexp((double)m, -9) : std::ldexp(1.0 + m / 8.0, e - 7);
+    if (b & 0x80) w = -w;
+    if (w != Jf[k]) j_fp8_exact = false;
+  }
   const int Mp_s = (int)round_up(n, 16);
   const int Kp_s = (int)round_up(n, bf ? 32 : 16);
   const int stride_s = (int)((round_up(Kp_s * es, 256) + 16) / es);
   const bool small_fits = Mp_s <= 256 && small_lds_bytes(c->prec, Mp_s, stride_s) <= (size_t)device_max_lds();
-  if (small_fits && !(p->flags & NMFA_FLAG_FORCE_STEP)) {
+  // persistent XCD-group kernel: BF16 operands, J rows in LDS as BF16 or (exact / FP8-J) FP8
+  const int Mp_x = (int)round_up(n, xcd_rows());
+  const int Kp_x = (int)round_up(n, 128);
+  const bool x_j8 = (c->prec == NMFA_FP8J_BF16S) || (Kp_x > 1024 && j_fp8_exact);
+  const bool x_ok = bf && Mp_x / xcd_rows() <= 32 && (x_j8 || Kp_x <= 1024) &&
+                    xcd_lds_bytes(x_j8, Kp_x) <= (size_t)device_max_lds();
+  if (p->flags & NMFA_FLAG_FORCE_STEP) {
+    c->path = 1;
+  } else if ((p->flags & NMFA_FLAG_FORCE_XCD) && x_ok) {
+    c->path = 2;
+  } else if ((p->flags & NMFA_FLAG_FORCE_XCD)) {
+    return fail(NMFA_EINVAL, "nmfa_create: the XCD-group kernel needs BF16 / FP8-J precision and n <= 2048");
+  } else if (small_fits) {
     c->path = 0;
+  } else if (x_ok) {
+    c->path = 2;
+  } else {
+    c->path = 1;
+  }
+  if (c->path == 0) {
     c->Mp = Mp_s;
     c->Kp = Kp_s;
     c->lds_stride = stride_s;
+  } else if (c->path == 2) {
+    c->Mp = Mp_x;
+    c->Kp = Kp_x;
+    c->lds_stride = 0;
+    c->j_fp8 = x_j8;
   } else {
-    c->path = 1;
     c->Mp = (int)round_up(n, 64);
     c->Kp = c->Mp;
     c->lds_stride = 0;
@@ -328,15 +313,15 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     hterm[i] = (c->prec == NMFA_FP64) ? hi : hi * inv[i];
   }
 
-  // operand copy of J
-  const bool j8_small = (c->prec == NMFA_FP8J_BF16S && c->path == 0);
-  const size_t jbytes = (size_t)Mp * Kp * (j8_small ? 1 : es);
+  // operand copy of J: FP8 bytes for the FP8-J kernels, else the precision's operand type
+  const bool j8_store = (c->prec == NMFA_FP8J_BF16S && c->path == 0) || (c->path == 2 && c->j_fp8);
+  const size_t jbytes = (size_t)Mp * Kp * (j8_store ? 1 : es);
   std::vector<unsigned char> jbuf(jbytes, 0);
   for (int i = 0; i < n; ++i) {
     for (int j = 0; j < n; ++j) {
       const double v = Jf[(size_t)i * n + j];
       const size_t idx = (size_t)i * Kp + j;
-      if (j8_small) {
+      if (j8_store) {
         jbuf[idx] = fp8e4m3_bits(v);
       } else if (c->prec == NMFA_FP64) {
         std::memcpy(&jbuf[idx * 8], &v, 8);
@@ -403,6 +388,10 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   CREATE_TRY(hipEventCreate(&c->ev0));
   CREATE_TRY(hipEventCreate(&c->ev1));
   CREATE_TRY(hipEventCreate(&c->evm));
+  if (c->path == 2) {
+    CREATE_TRY(hipMalloc(&c->d_ctl, (size_t)xcd_ctl_words() * 4));
+    CREATE_TRY(hipMemset(c->d_ctl, 0, (size_t)xcd_ctl_words() * 4));
+  }
 #undef CREATE_TRY
   *out = c;
   return NMFA_OK;
@@ -410,7 +399,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
 
 // Make sure the per-run buffers hold R replicas (contents are kept only if R is unchanged).
 static int ensure_run_buffers(nmfa_ctx* c, int R) {
-  const int Rp = (int)round_up(R, 64);
+  const int Rp = (int)round_up(R, 128);
   if (R > c->cap_R) {
     free_run_buffers(c);
     const size_t cnt = (size_t)R * c->n;
@@ -421,7 +410,7 @@ static int ensure_run_buffers(nmfa_ctx* c, int R) {
     c->cap_R = R;
     c->state_valid = false;
   }
-  if (c->path == 1 && Rp > c->cap_Rp) {
+  if ((c->path == 1 || c->path == 2) && Rp > c->cap_Rp) {
     (void)hipFree(c->d_S[0]);
     (void)hipFree(c->d_S[1]);
     c->d_S[0] = c->d_S[1] = nullptr;
@@ -454,8 +443,9 @@ static int ensure_coef(nmfa_ctx* c, int t_f) {
   return NMFA_OK;
 }
 
-extern "C" int nmfa_anneal_range(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end,
-                                 uint64_t seed, void* hip_stream) {
+// Validation, buffers and kernel arguments of one anneal call (shared with the serving scheduler).
+int ctx_prepare_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end, uint64_t seed,
+                    hipStream_t st, nmfa::AnnealArgs* out) {
   if (!c) return fail(NMFA_EINVAL, "nmfa_anneal: context is NULL");
   if (R < 1 || R > (1 << 24)) return fail(NMFA_EINVAL, "nmfa_anneal: R = %d outside [1, 2^24]", R);
   if (t_f < 1) return fail(NMFA_EINVAL, "nmfa_anneal: t_f = %d < 1", t_f);
@@ -464,7 +454,6 @@ extern "C" int nmfa_anneal_range(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_
   if (t_begin > 1 && !(c->state_valid && c->R == R))
     return fail(NMFA_ESTATE, "nmfa_anneal: t_begin > 1 needs the state of a previous call with R = %d", R);
   HIP_TRY(hipSetDevice(c->device));
-  hipStream_t st = (hipStream_t)hip_stream;
   int rc;
   if (c->R != R && c->cap_R >= R && t_begin == 1) c->state_valid = false;
   if ((rc = ensure_run_buffers(c, R)) != NMFA_OK) return rc;
@@ -510,12 +499,68 @@ extern "C" int nmfa_anneal_range(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_
   a.alpha = c->alpha;
   a.sigma = c->sigma;
   a.negate_noise = (c->flags & NMFA_FLAG_NEGATE_NOISE) ? 1 : 0;
+  c->traj_iters = rec;
+  *out = a;
+  return NMFA_OK;
+}
+
+// Energies of the readout and the completion bookkeeping of one anneal call.
+int ctx_finish_run(nmfa_ctx* c, hipStream_t st) {
+  HIP_TRY(launch_energy(c->d_J8, c->d_J64, c->d_h, c->h_integral ? 1 : 0, c->d_spins, c->n, c->R, c->d_Eint,
+                        c->d_E, st));
+  HIP_TRY(hipEventRecord(c->ev1, st));
+  c->timed = true;
+  c->state_valid = true;
+  c->result_valid = true;
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_anneal_range(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end,
+                                 uint64_t seed, void* hip_stream) {
+  return ctx_launch_run(c, R, t_f, t_begin, t_end, seed, (hipStream_t)hip_stream, true);
+}
+
+int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end, uint64_t seed,
+                   hipStream_t st, bool finish) {
+  AnnealArgs a{};
+  int rc = ctx_prepare_run(c, R, t_f, t_begin, t_end, seed, st, &a);
+  if (rc != NMFA_OK) return rc;
 
   HIP_TRY(hipEventRecord(c->ev0, st));
   if (c->path == 0) {
     HIP_TRY(launch_anneal_small(c->prec, a, st));
     c->launches = 1;
     HIP_TRY(hipEventRecord(c->evm, st));
+  } else if (c->path == 2) {
+    const int Rg = xcd_group_replicas();
+    const int G = (R + Rg - 1) / Rg;
+    const int P = c->Mp / xcd_rows();
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    const int per_launch = std::max(1, std::min(cus, 256) / P);  // the control block serves 256 workgroups
+    HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[t_begin & 1], c->n, R, c->Kp, G * Rg,
+                              t_begin == 1 ? 1 : 0, st));
+    HIP_TRY(hipMemsetAsync(c->d_ctl, 0, (size_t)xcd_ctl_words() * 4, st));
+    HIP_TRY(hipEventRecord(c->ev0, st));
+    c->launches = 0;
+    for (int gb = 0; gb < G; gb += per_launch) {
+      const int ng = std::min(per_launch, G - gb);
+      if (gb > 0) {  // fresh registration and barrier counters; the abort and mode words persist
+        HIP_TRY(hipMemsetAsync(c->d_ctl, 0, 17 * 4, st));
+        HIP_TRY(hipMemsetAsync(c->d_ctl + 64, 0, (size_t)(xcd_ctl_words() - 64) * 4, st));
+      }
+      XcdArgs x{};
+      x.S[0] = c->d_S[0];
+      x.S[1] = c->d_S[1];
+      x.ctl = c->d_ctl;
+      x.P = P;
+      x.group_base = gb;
+      x.force_fenced = (c->flags & NMFA_FLAG_FORCE_FENCED) ? 1 : 0;
+      HIP_TRY(launch_anneal_xcd(c->j_fp8, a, x, ng, st));
+      ++c->launches;
+    }
+    HIP_TRY(hipEventRecord(c->evm, st));
+    c->ctl_pending = true;
   } else {
     if (t_begin == 1) HIP_TRY(hipMemsetAsync(c->d_state, 0, (size_t)R * c->n * c->acc_size(), st));
     HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[0], c->n, R, c->Kp, a.Rp, t_begin == 1 ? 1 : 0, st));
@@ -529,14 +574,11 @@ extern "C" int nmfa_anneal_range(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_
     HIP_TRY(hipEventRecord(c->evm, st));
     HIP_TRY(launch_readout(c->prec, c->d_state, c->d_spins, (size_t)R * c->n, st));
   }
-  HIP_TRY(launch_energy(c->d_J8, c->d_J64, c->d_h, c->h_integral ? 1 : 0, c->d_spins, c->n, R, c->d_Eint,
-                        c->d_E, st));
-  HIP_TRY(hipEventRecord(c->ev1, st));
-  c->timed = true;
-  c->state_valid = true;
-  c->result_valid = true;
-  c->traj_iters = rec;
-  return NMFA_OK;
+  if (!finish) {
+    c->state_valid = true;
+    return NMFA_OK;
+  }
+  return ctx_finish_run(c, st);
 }
 
 extern "C" int nmfa_anneal(nmfa_ctx* c, int32_t R, int32_t t_f, uint64_t seed, void* hip_stream) {
@@ -547,6 +589,17 @@ static int sync_ctx(nmfa_ctx* c) {
   HIP_TRY(hipSetDevice(c->device));
   if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
   else HIP_TRY(hipDeviceSynchronize());
+  if (c->ctl_pending) {
+    unsigned flags[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpy(flags, c->d_ctl + 16, sizeof(flags), hipMemcpyDeviceToHost));
+    c->ctl_pending = false;
+    c->exchange_mode = (int)flags[2];
+    if (flags[1]) {
+      c->result_valid = false;
+      c->state_valid = false;
+      return fail(NMFA_EDEVICE, "XCD-group kernel: a group barrier or the start-up registration timed out");
+    }
+  }
   return NMFA_OK;
 }
 
@@ -670,7 +723,17 @@ extern "C" int nmfa_info(nmfa_ctx* c, int32_t* n, int32_t* precision, int32_t* p
   if (!c) return fail(NMFA_EINVAL, "nmfa_info: context is NULL");
   if (n) *n = c->n;
   if (precision) *precision = c->prec;
-  if (path) *path = c->path;
+  if (path) {
+    if (c->path == 2) {
+      if (c->ctl_pending) {
+        int rc = sync_ctx(c);
+        if (rc) return rc;
+      }
+      *path = (c->exchange_mode == 2) ? 3 : 2;
+    } else {
+      *path = c->path;
+    }
+  }
   return NMFA_OK;
 }
 

@@ -1,0 +1,75 @@
+// Internal: the solver context behind the opaque nmfa_ctx handle of include/nmfa.h, and the
+// pieces of the anneal call that the serving scheduler reuses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nmfa.h"
+#include "nmfa_internal.h"
+
+struct nmfa_ctx {
+  int n = 0;
+  int prec = NMFA_BF16;
+  int path = 0;  // 0 = persistent small-N kernel, 1 = per-iteration kernel, 2 = XCD-group kernel
+  bool j_fp8 = false;        // path 2: J rows held as FP8 in LDS
+  unsigned* d_ctl = nullptr; // path 2: control block
+  bool ctl_pending = false;  // path 2: abort/mode flags not yet read back
+  int exchange_mode = 0;     // path 2: 1 = XCD-local, 2 = device-scope fences
+  int Mp = 0, Kp = 0, lds_stride = 0;
+  double alpha = 0.15, sigma = 0.15;
+  uint32_t flags = 0;
+  int record = 0;
+  std::vector<double> ku, kT;
+  std::vector<double> h;  // empty if h = 0
+  bool has_h = false;
+  bool J_integral = false, h_integral = true;
+  double w_total = 0.0;  // sum_{i<j} J_ij
+  int device = 0;
+
+  // device data of the instance
+  void* d_J = nullptr;       // operand layout of the selected path
+  void* d_inv = nullptr;     // [Mp] acc_t
+  void* d_hterm = nullptr;   // [Mp] acc_t
+  int8_t* d_J8 = nullptr;    // [n][n] for exact energies (integral |J| <= 127)
+  double* d_J64 = nullptr;   // [n][n] otherwise
+  double* d_h = nullptr;     // [n] or null
+
+  // per-run buffers
+  int cap_R = 0;             // replicas the buffers hold
+  int R = 0, t_f = 0;        // current run
+  uint64_t seed = 0;
+  bool state_valid = false;
+  bool result_valid = false;
+  int traj_iters = 0;        // iterations recorded by the last call
+  void* d_state = nullptr;   // [R][n] acc_t
+  int8_t* d_spins = nullptr; // [R][n]
+  double* d_E = nullptr;     // [R]
+  long long* d_Eint = nullptr;
+  void* d_S[2] = {nullptr, nullptr};  // per-iteration path: [Rp][Kp] op_t
+  int cap_Rp = 0;
+  void* d_traj = nullptr;
+  size_t traj_cap = 0;
+  void* d_coef = nullptr;
+  int coef_tf = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
+  int launches = 0;
+  bool timed = false;
+
+  size_t acc_size() const { return prec == NMFA_FP64 ? 8 : 4; }
+  size_t op_size() const { return prec == NMFA_FP64 ? 8 : (prec == NMFA_FP32 ? 4 : 2); }
+};
+
+// Validate one anneal call, make its buffers and fill the kernel arguments (no launch).
+int ctx_prepare_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end, uint64_t seed,
+                    hipStream_t st, nmfa::AnnealArgs* out);
+// Enqueue iterations t_begin..t_end on the context's kernel path; with finish, also the energies.
+int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end, uint64_t seed,
+                   hipStream_t st, bool finish);
+// Enqueue the energies of the readout and mark the results valid.
+int ctx_finish_run(nmfa_ctx* c, hipStream_t st);
+// Record an error message for nmfa_last_error() and return code.
+int nmfa_fail(int code, const char* fmt, ...);

@@ -26,7 +26,25 @@ struct AnnealArgs {
   int negate_noise;      // test hook: z -> -z
 };
 
+// Persistent large-N kernel (XCD groups): extra arguments.
+struct XcdArgs {
+  void* S[2];        // operand copies of the spins, BF16 [Rp][Kp], double-buffered by parity of t
+  unsigned* ctl;     // control block (xcd_ctl_words() words, zeroed before every launch)
+  int P;             // workgroups per replica group = Mp / xcd_rows()
+  int group_base;    // first replica group of this launch
+  int force_fenced;  // test hook: use device-scope fences even when the groups are XCD-local
+};
+
 hipError_t launch_anneal_small(int prec, const AnnealArgs& a, hipStream_t st);
+// jobs: device array of AnnealArgs (one per job); tasks: device array of (job, replica block).
+hipError_t launch_anneal_small_batched(int prec, const AnnealArgs* jobs, const int2* tasks, int n_tasks,
+                                       int max_Mp, size_t lds, hipStream_t st);
+hipError_t launch_anneal_xcd(bool j_fp8, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
+size_t xcd_lds_bytes(bool j_fp8, int Kp);
+int xcd_ctl_words();
+int xcd_rows();
+int xcd_group_replicas();
+int xcd_chunk();
 size_t small_lds_bytes(int prec, int Mp, int stride);
 hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
                               hipStream_t st);

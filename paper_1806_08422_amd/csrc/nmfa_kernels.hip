@@ -83,9 +83,12 @@ struct Epilogue<PREC_BF16> : EpilogueF32<PREC_BF16> {};
 // [16w, 16w+16); grid = ceil(R / 16) workgroups, workgroup b owns replicas [16b, 16b+16).
 // LDS: Js[Mp][js] (op_t), Ss[2][16][js] (op_t), with js = padded row stride in elements.
 // J8: the global copy of J is FP8 e4m3 and is widened to BF16 while it is staged into LDS.
+// The body is shared with anneal_small_batched, where one launch carries replica blocks of many
+// jobs (serving): a workgroup may then have more waves than its job has row tiles, and the extra
+// waves only take part in the barriers.
 // ------------------------------------------------------------------------------------------
 template <int P, bool J8>
-__global__ __launch_bounds__(1024) void anneal_small(AnnealArgs a) {
+__device__ __forceinline__ void anneal_small_body(const AnnealArgs& a, const int rblock) {
   using Tr = Traits<P>;
   using op_t = typename Tr::op_t;
   using acc_t = typename Tr::acc_t;
@@ -104,7 +107,8 @@ __global__ __launch_bounds__(1024) void anneal_small(AnnealArgs a) {
   const int wave = tid >> 6;
   const int g = lane >> 4;
   const int c = lane & 15;
-  const int r = blockIdx.x * 16 + c;  // replica of this lane
+  const int r = rblock * 16 + c;       // replica of this lane
+  const bool act = wave < (Mp >> 4);   // this wave owns a row tile of the job
   const int row0 = wave * 16 + 4 * g;  // first of this lane's four rows (accumulator layout)
   const int arow = wave * 16 + Tr::a_row(c);  // row this lane supplies to the A operand
   const int Kq = Kp >> 2;
@@ -142,16 +146,16 @@ __global__ __launch_bounds__(1024) void anneal_small(AnnealArgs a) {
   const acc_t* inv_g = reinterpret_cast<const acc_t*>(a.inv_norm);
   const acc_t* h_g = reinterpret_cast<const acc_t*>(a.hterm);
   acc_t* state = reinterpret_cast<acc_t*>(a.state);
-  const bool live_r = r < a.R;
+  const bool live_r = act && r < a.R;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    inv[v] = inv_g[row0 + v];
-    hv[v] = h_g[row0 + v];
+    inv[v] = act ? inv_g[row0 + v] : (acc_t)0;
+    hv[v] = act ? h_g[row0 + v] : (acc_t)0;
     const bool live = live_r && (row0 + v) < N;
     s[v] = (a.load_state && live) ? state[(size_t)r * N + row0 + v] : (acc_t)0;
   }
   __syncthreads();
-  if (a.load_state) {
+  if (a.load_state && act) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) Ss[(size_t)c * js + row0 + v] = (op_t)s[v];
   }
@@ -161,6 +165,10 @@ __global__ __launch_bounds__(1024) void anneal_small(AnnealArgs a) {
   acc_t* traj = reinterpret_cast<acc_t*>(a.traj);
   int cur = 0;
   for (int t = a.t_begin; t <= a.t_end; ++t) {
+    if (!act) {  // spare wave of a batched launch
+      __syncthreads();
+      continue;
+    }
     // ---- mean field: D = J[rows of this wave] . S[:, replicas of this block] ----------------
     acc4_t acc;
 #pragma unroll
@@ -208,6 +216,20 @@ __global__ __launch_bounds__(1024) void anneal_small(AnnealArgs a) {
       }
     }
   }
+}
+
+template <int P, bool J8>
+__global__ __launch_bounds__(1024) void anneal_small(AnnealArgs a) {
+  anneal_small_body<P, J8>(a, (int)blockIdx.x);
+}
+
+// One launch for replica blocks of many jobs: tasks[b] = (job index, replica block).
+template <int P, bool J8>
+__global__ __launch_bounds__(1024) void anneal_small_batched(const AnnealArgs* __restrict__ jobs,
+                                                             const int2* __restrict__ tasks) {
+  const int2 tk = tasks[blockIdx.x];
+  const AnnealArgs a = jobs[tk.x];
+  anneal_small_body<P, J8>(a, tk.y);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -478,6 +500,27 @@ hipError_t launch_anneal_small(int prec, const AnnealArgs& a, hipStream_t st) {
     case PREC_FP32: return launch_small_t<PREC_FP32, false>(a, st);
     case PREC_BF16: return launch_small_t<PREC_BF16, false>(a, st);
     case PREC_FP8J_BF16S: return launch_small_t<PREC_BF16, true>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P, bool J8>
+static hipError_t launch_small_batched_t(const AnnealArgs* jobs, const int2* tasks, int n_tasks, int max_Mp,
+                                         size_t lds, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void*)anneal_small_batched<P, J8>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((anneal_small_batched<P, J8>), dim3(n_tasks), dim3(64 * (max_Mp / 16)), lds, st, jobs, tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_anneal_small_batched(int prec, const AnnealArgs* jobs, const int2* tasks, int n_tasks, int max_Mp,
+                                       size_t lds, hipStream_t st) {
+  switch (prec) {
+    case PREC_FP64: return launch_small_batched_t<PREC_FP64, false>(jobs, tasks, n_tasks, max_Mp, lds, st);
+    case PREC_FP32: return launch_small_batched_t<PREC_FP32, false>(jobs, tasks, n_tasks, max_Mp, lds, st);
+    case PREC_BF16: return launch_small_batched_t<PREC_BF16, false>(jobs, tasks, n_tasks, max_Mp, lds, st);
+    case PREC_FP8J_BF16S: return launch_small_batched_t<PREC_BF16, true>(jobs, tasks, n_tasks, max_Mp, lds, st);
   }
   return hipErrorInvalidValue;
 }

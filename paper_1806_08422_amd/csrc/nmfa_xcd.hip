@@ -1,0 +1,328 @@
+// Persistent large-N NMFA kernel for gfx950: replica groups annealed by the workgroups of one XCD.
+//
+// Algorithm 1 (paper Sec. II) is synchronous: every iteration needs all N spins of the previous
+// one. For large N a replica group is therefore spread over P workgroups (one per CU) that each
+// own 64 rows of J; after each iteration the group exchanges its new spins through memory and
+// meets at a barrier.
+//
+//   * J: the workgroup's 64 rows stay in LDS for the whole anneal (FP8 E4M3, or BF16 when it
+//     fits), 8/16-byte chunks XOR-swizzled by row so that the A-fragment reads are conflict free.
+//   * S: the operand copy (BF16) of the group's spins lives in global memory, double-buffered by
+//     iteration parity, layout [replica][Kp]. Each iteration the workgroup streams it through
+//     LDS in chunks of 64 k with the direct-to-LDS loads of gfx950 (global_load_lds_dwordx4),
+//     double-buffered so the next chunk loads while the MFMAs consume the current one.
+//   * Wave (a, b) of the 4 waves computes 32 rows (two 16-row tiles) x 64 replicas (four 16-column
+//     tiles) with v_mfma_f32_16x16x32_bf16; FP8 J is widened to BF16 in registers
+//     (v_cvt_scalef32_pk_bf16_fp8, one A fragment reused for four MFMAs).
+//   * The epilogue (normalisation, Philox noise, tanh, damped update) runs in registers on the
+//     accumulator layout; the FP32 master state never leaves the registers between iterations.
+//   * Barrier: the P workgroups of a group count arrivals with a device-scope atomic and poll it
+//     with device-scope loads. When every group sits inside one XCD (checked at start-up from
+//     the XCC_ID hardware register) the new spins are exchanged through that XCD's L2: stores
+//     complete before the arrival, and readers invalidate their L1 after the barrier. Otherwise
+//     the workgroups fall back to device-scope release/acquire fences.
+//   * Every wait is bounded; a timeout raises an abort flag that ends every workgroup's loop and
+//     is reported to the host as an error.
+#include <hip/hip_runtime.h>
+
+#include "nmfa_device.h"
+#include "nmfa_internal.h"
+
+namespace nmfa {
+
+// control block layout (uint32 words)
+enum : int {
+  CTL_REG = 0,        // [16] workgroups registered per XCD
+  CTL_TOTAL = 16,     // workgroups registered
+  CTL_ABORT = 17,     // barrier timeout
+  CTL_MODE = 18,      // 1 = XCD-local exchange, 2 = device-scope fences (written by workgroup 0)
+  CTL_BAR = 64,       // group barrier counters, one per 16 words
+  CTL_WG = 64 + 16 * 256,  // per workgroup: group, row block, exchange mode (4 words each)
+  CTL_WORDS = 64 + 16 * 256 + 4 * 256,
+};
+
+constexpr int XCD_ROWS = 64;   // rows of J per workgroup
+constexpr int XCD_RG = 128;    // replicas per group
+constexpr int XCD_KC = 64;     // k per streamed chunk
+constexpr unsigned SPIN_LIMIT = 1u << 22;  // about a second of polling
+
+__device__ __forceinline__ unsigned ld_dev(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Widen 8 FP8 E4M3 values (two 32-bit words) to 8 BF16 (exact for every FP8 value).
+__device__ __forceinline__ bf16x8 fp8x8_to_bf16x8(uint32_t lo, uint32_t hi) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, false);
+  const bf16x2 p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, true);
+  const bf16x2 p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, false);
+  const bf16x2 p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, true);
+  bf16x8 r;
+  r[0] = p0[0]; r[1] = p0[1]; r[2] = p1[0]; r[3] = p1[1];
+  r[4] = p2[0]; r[5] = p2[1]; r[6] = p3[0]; r[7] = p3[1];
+  return r;
+}
+
+template <bool J_FP8>
+__global__ __launch_bounds__(256, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
+  extern __shared__ __align__(16) unsigned char smem[];  // all of LDS: J rows + S chunks
+  constexpr int JES = J_FP8 ? 1 : 2;  // bytes per J element in LDS
+  const int N = a.N, Kp = a.Kp, P = x.P;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g4 = lane >> 4, c = lane & 15;
+  const int wa = wave >> 1, wb = wave & 1;  // rows 32*wa.., replicas 64*wb..
+  unsigned* ctl = x.ctl;
+
+  // ---- registration: find the XCD of every workgroup, then agree on the mapping -------------
+  if (tid == 0) {
+    const unsigned xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | (15 << 11)) & 0xfu;
+    const unsigned slot = atomicAdd(&ctl[CTL_REG + xcc], 1u);
+    atomicAdd(&ctl[CTL_TOTAL], 1u);
+    unsigned spins = 0;
+    while (ld_dev(&ctl[CTL_TOTAL]) < gridDim.x) {
+      if (++spins > SPIN_LIMIT) {
+        atomicExch(&ctl[CTL_ABORT], 1u);
+        break;
+      }
+    }
+    // XCD-local exchange needs every XCD's workgroup count to be a multiple of P.
+    unsigned base = 0, ok = 1;
+    for (unsigned k = 0; k < 16; ++k) {
+      const unsigned cnt = ld_dev(&ctl[CTL_REG + k]);
+      if (cnt % (unsigned)P) ok = 0;
+      if (k < xcc) base += cnt;
+    }
+    unsigned* info = &ctl[CTL_WG + 4 * blockIdx.x];
+    info[0] = ok ? (base + slot) / (unsigned)P : blockIdx.x / (unsigned)P;
+    info[1] = ok ? slot % (unsigned)P : blockIdx.x % (unsigned)P;
+    info[2] = (ok && !x.force_fenced) ? 1u : 0u;
+    if (blockIdx.x == 0) atomicMax(&ctl[CTL_MODE], (ok && !x.force_fenced) ? 1u : 2u);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+  // broadcast through this workgroup's words of the control block (device-scope loads)
+  const unsigned my_group = ld_dev(&ctl[CTL_WG + 4 * blockIdx.x]);
+  const int group = (int)my_group + x.group_base;
+  const int rb = (int)ld_dev(&ctl[CTL_WG + 4 * blockIdx.x + 1]);
+  const bool xcd_mode = ld_dev(&ctl[CTL_WG + 4 * blockIdx.x + 2]) != 0;
+  bool aborted = ld_dev(&ctl[CTL_ABORT]) != 0;
+
+  // ---- LDS: J rows (swizzled), two S chunk buffers ----------------------------------------
+  unsigned char* Jl = smem;                              // [64][Kp * JES]
+  unsigned char* Sl = smem + (size_t)XCD_ROWS * Kp * JES;  // [2][128][64] bf16
+  {
+    // J chunks: 8 bytes (FP8) or 16 bytes (BF16); swizzle chunk index with the row
+    const int chunk_bytes = J_FP8 ? 8 : 16;
+    const int chunks_per_row = Kp * JES / chunk_bytes;
+    const unsigned char* Jg = reinterpret_cast<const unsigned char*>(a.J) + (size_t)rb * XCD_ROWS * Kp * JES;
+    for (int idx = tid; idx < XCD_ROWS * chunks_per_row; idx += 256) {
+      const int row = idx / chunks_per_row, ch = idx - row * chunks_per_row;
+      const int sw = J_FP8 ? (ch ^ (row & 15)) : (ch ^ (row & 7));
+      if (J_FP8) {
+        *reinterpret_cast<uint2*>(Jl + (size_t)row * Kp + sw * 8) =
+            *reinterpret_cast<const uint2*>(Jg + (size_t)row * Kp + ch * 8);
+      } else {
+        *reinterpret_cast<uint4*>(Jl + (size_t)row * Kp * 2 + sw * 16) =
+            *reinterpret_cast<const uint4*>(Jg + (size_t)row * Kp * 2 + ch * 16);
+      }
+    }
+  }
+
+  // ---- per-lane constants and state ----------------------------------------------------------
+  const float* inv_g = reinterpret_cast<const float*>(a.inv_norm);
+  const float* h_g = reinterpret_cast<const float*>(a.hterm);
+  float* state = reinterpret_cast<float*>(a.state);
+  float* traj = reinterpret_cast<float*>(a.traj);
+  const float* coef = reinterpret_cast<const float*>(a.coef);
+  float inv[2][4], hv[2][4], s[2][4][4];
+  int row0[2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    row0[rt] = rb * XCD_ROWS + 32 * wa + 16 * rt + 4 * g4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      inv[rt][v] = inv_g[row0[rt] + v];
+      hv[rt][v] = h_g[row0[rt] + v];
+    }
+  }
+  const int rgroup0 = group * XCD_RG + 64 * wb;  // first replica of this wave
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int r = rgroup0 + 16 * ct + c;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0[rt] + v;
+        s[rt][ct][v] = (a.load_state && r < a.R && i < N) ? state[(size_t)r * N + i] : 0.0f;
+      }
+  }
+
+  const float sg = (float)a.sigma;
+  const float neg2ln2_s2 = -2.0f * 0.6931471805599453f * sg * sg;
+  const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha);
+  const int nchunks = Kp / XCD_KC;
+  __bf16* S0 = reinterpret_cast<__bf16*>(x.S[0]);
+  __bf16* S1 = reinterpret_cast<__bf16*>(x.S[1]);
+  unsigned* bar = &ctl[CTL_BAR + 16 * (int)my_group];  // per launch: < 256 groups
+  int epoch = 0;
+  __syncthreads();
+
+  for (int t = a.t_begin; t <= a.t_end && !aborted; ++t) {
+    const __bf16* Scur = (t & 1) ? S1 : S0;
+    __bf16* Snext = (t & 1) ? S0 : S1;
+    const __bf16* Sgrp = Scur + (size_t)group * XCD_RG * Kp;
+
+    // DMA of one chunk: 128 replicas x 64 k (16 KB) = 16 wave-instructions of 1 KB; wave w issues
+    // replica blocks 4w..4w+3 (8 replicas each). Lane l fills LDS position (l/8, l%8) of its block
+    // with global column (l%8) ^ (replica & 7).
+    auto issue_chunk = [&](int ch, int buf) {
+      unsigned char* dst = Sl + (size_t)buf * XCD_RG * XCD_KC * 2;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int blk = 4 * wave + u;
+        const int rep = blk * 8 + (lane >> 3);
+        const int col = (lane & 7) ^ (rep & 7);
+        const __bf16* src = Sgrp + (size_t)rep * Kp + ch * XCD_KC + col * 8;
+        __builtin_amdgcn_global_load_lds(src, dst + (size_t)blk * 1024, 16, 0, 0);
+      }
+    };
+
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
+
+    issue_chunk(0, 0);
+    for (int ch = 0; ch < nchunks; ++ch) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's DMA of chunk ch has landed
+      __syncthreads();               // ... and every wave's; buffer (ch+1)&1 is free again
+      if (ch + 1 < nchunks) issue_chunk(ch + 1, (ch + 1) & 1);
+      const unsigned char* Sb = Sl + (size_t)(ch & 1) * XCD_RG * XCD_KC * 2;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const int kk = ch * XCD_KC + 32 * ks + 8 * g4;  // k of this lane group within Kp
+        bf16x8 af[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+          const int lrow = 32 * wa + 16 * rt + c;
+          if (J_FP8) {
+            const int chunk = kk >> 3;
+            const int sw = (chunk & ~15) | ((chunk & 15) ^ (lrow & 15));
+            const uint2 raw = *reinterpret_cast<const uint2*>(Jl + (size_t)lrow * Kp + sw * 8);
+            af[rt] = fp8x8_to_bf16x8(raw.x, raw.y);
+          } else {
+            const int chunk = kk >> 3;
+            const int sw = (chunk & ~7) | ((chunk & 7) ^ (lrow & 7));
+            af[rt] = *reinterpret_cast<const bf16x8*>(Jl + (size_t)lrow * Kp * 2 + sw * 16);
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          const int rep = 64 * wb + 16 * ct + c;
+          const int col = (4 * ks + g4) ^ (rep & 7);
+          const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(Sb + (size_t)rep * 128 + col * 16);
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rt], bfr, acc[rt][ct], 0, 0, 0);
+        }
+      }
+    }
+
+    // ---- fused epilogue --------------------------------------------------------------------
+    const float coef_t = coef[t - 1];
+    const int k_rec = t - a.t_begin;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int r = rgroup0 + 16 * ct + c;
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        float z[4];
+        sigma_gauss4_f32(philox4x32_10((uint32_t)(row0[rt] >> 2), (uint32_t)r, (uint32_t)t, 0u, a.key0, a.key1),
+                         neg2ln2_s2, z);
+        __bf16 outv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float xf = fmaf(acc[rt][ct][v], inv[rt][v], hv[rt][v]);
+          const float phi = a.negate_noise ? xf - z[v] : xf + z[v];
+          const float sh = neg_tanh_from_exp2_arg(phi * coef_t);
+          float sv = fmaf(alpha, sh, oma * s[rt][ct][v]);
+          if (row0[rt] + v >= N) sv = 0.0f;
+          s[rt][ct][v] = sv;
+          outv[v] = (__bf16)sv;
+        }
+        *reinterpret_cast<uint2*>(Snext + (size_t)r * Kp + row0[rt]) = *reinterpret_cast<const uint2*>(outv);
+        if (traj && k_rec < a.record && r < a.R) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (row0[rt] + v < N) traj[((size_t)k_rec * a.R + r) * N + row0[rt] + v] = s[rt][ct][v];
+        }
+      }
+    }
+
+    // ---- group barrier ----------------------------------------------------------------------
+    if (t < a.t_end) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's stores of the new spins are complete
+      __syncthreads();
+      ++epoch;
+      if (tid == 0) {
+        if (!xcd_mode) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (unsigned)P * (unsigned)epoch;
+        unsigned spins = 0;
+        while (ld_dev(bar) < target) {
+          if (++spins > SPIN_LIMIT || ld_dev(&ctl[CTL_ABORT])) {
+            atomicExch(&ctl[CTL_ABORT], 1u);
+            break;
+          }
+        }
+        if (!xcd_mode) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      __syncthreads();
+      if (xcd_mode) asm volatile("buffer_inv sc0" ::: "memory");  // drop stale L1 lines
+      aborted = ld_dev(&ctl[CTL_ABORT]) != 0;
+    }
+  }
+
+  // ---- final state and readout ---------------------------------------------------------------
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int r = rgroup0 + 16 * ct + c;
+    if (r >= a.R) continue;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0[rt] + v;
+        if (i < N) {
+          state[(size_t)r * N + i] = s[rt][ct][v];
+          if (a.spins) a.spins[(size_t)r * N + i] = (s[rt][ct][v] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
+        }
+      }
+  }
+}
+
+size_t xcd_lds_bytes(bool j_fp8, int Kp) {
+  return (size_t)XCD_ROWS * Kp * (j_fp8 ? 1 : 2) + 2 * (size_t)XCD_RG * XCD_KC * 2;
+}
+
+int xcd_ctl_words() { return CTL_WORDS; }
+int xcd_rows() { return XCD_ROWS; }
+int xcd_group_replicas() { return XCD_RG; }
+int xcd_chunk() { return XCD_KC; }
+
+hipError_t launch_anneal_xcd(bool j_fp8, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
+  const size_t lds = xcd_lds_bytes(j_fp8, a.Kp);
+  const void* fn = j_fp8 ? (const void*)anneal_xcd<true> : (const void*)anneal_xcd<false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  AnnealArgs aa = a;
+  XcdArgs xx = x;
+  void* args[] = {&aa, &xx};
+  return hipLaunchCooperativeKernel(fn, dim3(groups * x.P), dim3(256), args, lds, st);
+}
+
+}  // namespace nmfa

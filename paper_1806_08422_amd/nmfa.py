@@ -30,14 +30,21 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp8j_bf16s": FP8J_BF16S
 FLAG_NEGATE_NOISE = 0x1
 FLAG_UPPER_TRIANGULAR = 0x2
 FLAG_FORCE_STEP = 0x4
+FLAG_FORCE_XCD = 0x8
+FLAG_FORCE_FENCED = 0x10
+PATHS = ("persistent", "step", "xcd", "xcd_fenced")
 
 # Every function declared in include/nmfa.h (checked by the CPU tests against the header).
 EXPORTS = (
     "nmfa_params_default", "nmfa_create", "nmfa_anneal", "nmfa_anneal_range", "nmfa_spins",
     "nmfa_energies", "nmfa_cuts", "nmfa_energies_of", "nmfa_get_state", "nmfa_set_state",
     "nmfa_trajectory", "nmfa_info", "nmfa_last_timing", "nmfa_destroy", "nmfa_noise_words",
-    "nmfa_noise_values", "nmfa_last_error",
+    "nmfa_noise_values", "nmfa_last_error", "nmfa_server_params_default", "nmfa_server_create",
+    "nmfa_server_submit", "nmfa_server_poll", "nmfa_server_wait", "nmfa_server_result",
+    "nmfa_server_release", "nmfa_server_cancel", "nmfa_server_stats_get", "nmfa_server_destroy",
 )
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 
 
 class NmfaError(RuntimeError):
@@ -58,6 +65,22 @@ class Params(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("record_iters", ctypes.c_int32),
     ]
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("precision", ctypes.c_uint32),
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("max_active", ctypes.c_int32),
+        ("chunk_iters", ctypes.c_int32),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "submitted", "completed", "failed", "cancelled", "queued", "active", "bytes_in_use",
+        "peak_bytes", "rounds", "batched_launches")]
 
 
 def _load() -> ctypes.CDLL:
@@ -84,6 +107,16 @@ def _load() -> ctypes.CDLL:
         "nmfa_noise_words": ([u64, i32, i32, i32, i32, vp], ctypes.c_int),
         "nmfa_noise_values": ([u64, i32, i32, i32, i32, i32, vp], ctypes.c_int),
         "nmfa_last_error": ([], ctypes.c_char_p),
+        "nmfa_server_params_default": ([ctypes.POINTER(ServerParams)], None),
+        "nmfa_server_create": ([ctypes.POINTER(ServerParams), ctypes.POINTER(vp)], ctypes.c_int),
+        "nmfa_server_submit": ([vp, i32, vp, vp, i32, i32, u64, ctypes.POINTER(u64)], ctypes.c_int),
+        "nmfa_server_poll": ([vp, u64, ctypes.POINTER(i32)], ctypes.c_int),
+        "nmfa_server_wait": ([vp, u64, i32], ctypes.c_int),
+        "nmfa_server_result": ([vp, u64, vp, vp, vp, vp], ctypes.c_int),
+        "nmfa_server_release": ([vp, u64], ctypes.c_int),
+        "nmfa_server_cancel": ([vp, u64], ctypes.c_int),
+        "nmfa_server_stats_get": ([vp, ctypes.POINTER(ServerStats)], ctypes.c_int),
+        "nmfa_server_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -123,7 +156,7 @@ class Solver:
                  alpha: float = 0.15, sigma: float = 0.15,
                  knots: Optional[Sequence[Tuple[float, float]]] = None, record_iters: int = 0,
                  negate_noise: bool = False, upper_triangular: bool = False,
-                 force_step: bool = False):
+                 force_step: bool = False, force_xcd: bool = False, force_fenced: bool = False):
         J = np.ascontiguousarray(J, dtype=np.float64)
         if J.ndim != 2 or J.shape[0] != J.shape[1]:
             raise ValueError("J must be a square matrix")
@@ -142,6 +175,10 @@ class Solver:
             flags |= FLAG_UPPER_TRIANGULAR
         if force_step:
             flags |= FLAG_FORCE_STEP
+        if force_xcd:
+            flags |= FLAG_FORCE_XCD
+        if force_fenced:
+            flags |= FLAG_FORCE_FENCED
         p.flags = flags
         if knots is not None:
             ku = np.ascontiguousarray([k[0] for k in knots], dtype=np.float64)
@@ -233,7 +270,7 @@ class Solver:
     def info(self) -> dict:
         n, p, path = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib.nmfa_info(self._h, ctypes.byref(n), ctypes.byref(p), ctypes.byref(path)))
-        return {"n": n.value, "precision": p.value, "path": ("persistent", "step")[path.value]}
+        return {"n": n.value, "precision": p.value, "path": PATHS[path.value]}
 
     def last_timing(self) -> dict:
         a, t, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
@@ -253,3 +290,79 @@ def noise_values(seed: int, t: int, r0: int, n_rep: int, n_quads: int, fp64: boo
     _check(lib.nmfa_noise_values(int(seed), int(t), int(r0), int(n_rep), int(n_quads),
                                  int(bool(fp64)), _ptr(out)))
     return out
+
+
+class Server:
+    """Continuous-batching annealing server (nmfa_server_* in include/nmfa.h)."""
+
+    def __init__(self, precision="bf16", hbm_budget_bytes: int = 8 << 30, max_active: int = 256,
+                 chunk_iters: int = 250):
+        p = ServerParams()
+        lib.nmfa_server_params_default(ctypes.byref(p))
+        p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        p.hbm_budget_bytes = int(hbm_budget_bytes)
+        p.max_active = int(max_active)
+        p.chunk_iters = int(chunk_iters)
+        h = ctypes.c_void_p()
+        _check(lib.nmfa_server_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self._meta = {}
+
+    def submit(self, J: np.ndarray, h: Optional[np.ndarray], R: int, t_f: int, seed: int) -> int:
+        J = np.ascontiguousarray(J, dtype=np.float64)
+        hh = None if h is None else np.ascontiguousarray(h, dtype=np.float64)
+        t = ctypes.c_uint64()
+        _check(lib.nmfa_server_submit(self._h, int(J.shape[0]), _ptr(J), _ptr(hh), int(R), int(t_f),
+                                      int(seed) & (2**64 - 1), ctypes.byref(t)))
+        self._meta[t.value] = (int(J.shape[0]), int(R))
+        return int(t.value)
+
+    def poll(self, ticket: int) -> int:
+        st = ctypes.c_int32()
+        _check(lib.nmfa_server_poll(self._h, int(ticket), ctypes.byref(st)))
+        return int(st.value)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> bool:
+        rc = lib.nmfa_server_wait(self._h, int(ticket), int(timeout_ms))
+        if rc == NMFA_ESTATE:
+            return False
+        _check(rc)
+        return True
+
+    def result(self, ticket: int, spins: bool = False):
+        n, R = self._meta[int(ticket)]
+        E = np.zeros(R)
+        Ei = np.zeros(R, dtype=np.int64)
+        sp = np.zeros((R, n), dtype=np.int8) if spins else None
+        lat = ctypes.c_double()
+        _check(lib.nmfa_server_result(self._h, int(ticket), _ptr(E), _ptr(Ei), _ptr(sp), ctypes.byref(lat)))
+        return {"E": E, "E_int": Ei, "spins": sp, "latency_ms": float(lat.value)}
+
+    def release(self, ticket: int) -> None:
+        _check(lib.nmfa_server_release(self._h, int(ticket)))
+        self._meta.pop(int(ticket), None)
+
+    def cancel(self, ticket: int) -> None:
+        _check(lib.nmfa_server_cancel(self._h, int(ticket)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib.nmfa_server_stats_get(self._h, ctypes.byref(st)))
+        return {name: int(getattr(st, name)) for name, _ in ServerStats._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.nmfa_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

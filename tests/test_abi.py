@@ -67,3 +67,15 @@ def test_rejects_bad_parameters_and_schedules():
     assert _create_rc(J, knots=[(0.0, 1.0), (0.5, 0.5), (0.4, 0.2), (1.0, 0.1)])[0] == -1
     assert _create_rc(J, knots=[(0.1, 1.0), (1.0, 0.5)])[0] == -1
     assert _create_rc(J, precision=7)[0] == -1
+
+
+def test_server_rejects_bad_parameters():
+    from paper_1806_08422_amd import nmfa
+
+    with pytest.raises(nmfa.NmfaError) as ei:
+        nmfa.Server(max_active=0)
+    assert ei.value.code == -1
+    with pytest.raises(nmfa.NmfaError):
+        nmfa.Server(chunk_iters=0)
+    with pytest.raises(nmfa.NmfaError):
+        nmfa.Server(precision=9)

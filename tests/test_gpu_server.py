@@ -1,0 +1,101 @@
+"""Serving (continuous batching) on the GPU through the C ABI.
+
+* each request's result is bit-identical alone (nmfa_anneal) and inside a mixed stream served
+  with admission by a memory budget, chunked rounds and batched launches;
+* admission never holds more than the budget; a request larger than the budget fails cleanly;
+* requests that arrive while others run are admitted and finish;
+* cancellation of queued and running requests.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import instances
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nmfa():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_08422_amd import nmfa as m
+
+    return m
+
+
+def _mix():
+    jobs = []
+    for k, (kind, n, R, t_f) in enumerate([("sk", 60, 64, 500), ("reg", 150, 128, 700), ("sk", 100, 256, 600),
+                                           ("sk", 300, 64, 400), ("reg", 40, 96, 900), ("sk", 700, 128, 300),
+                                           ("sk", 20, 33, 450), ("reg", 256, 64, 520)]):
+        inst = instances.sk(n, 10 + k) if kind == "sk" else instances.random_regular(n, 3 + k % 5, 20 + k)
+        if k % 3 == 1:
+            inst.h = instances.gaussian_fields(inst.n, 0.5, 5 + k)
+        jobs.append((inst, R, t_f, 7000 + k))
+    return jobs
+
+
+def test_alone_equals_in_the_mix(nmfa):
+    jobs = _mix()
+    alone = []
+    for inst, R, t_f, seed in jobs:
+        with nmfa.Solver(inst.J, inst.h, precision="bf16") as s:
+            s.anneal(R, t_f, seed)
+            alone.append((s.energies()[0], s.spins()))
+    with nmfa.Server(precision="bf16", hbm_budget_bytes=64 << 20, max_active=4, chunk_iters=128) as srv:
+        tickets = []
+        for k, (inst, R, t_f, seed) in enumerate(jobs):
+            tickets.append(srv.submit(inst.J, inst.h, R, t_f, seed))
+            if k == 3:
+                time.sleep(0.05)  # later requests arrive while the first ones run
+        for t in tickets:
+            assert srv.wait(t, 120000)
+        for (E, sp), t in zip(alone, tickets):
+            res = srv.result(t, spins=True)
+            assert np.array_equal(res["E"], E)
+            assert np.array_equal(res["spins"], sp)
+            assert res["latency_ms"] > 0
+        st = srv.stats()
+        assert st["completed"] == len(jobs) and st["failed"] == 0
+        assert st["peak_bytes"] <= 64 << 20
+        assert st["batched_launches"] >= 1 and st["rounds"] >= 2
+
+
+def test_energies_in_the_mix_are_exact(nmfa):
+    jobs = _mix()[:4]
+    with nmfa.Server(precision="bf16") as srv:
+        tickets = [srv.submit(inst.J, inst.h, R, t_f, seed) for inst, R, t_f, seed in jobs]
+        for (inst, R, t_f, seed), t in zip(jobs, tickets):
+            assert srv.wait(t, 120000)
+            res = srv.result(t, spins=True)
+            assert np.array_equal(res["E"], oracle.energies(inst.J, inst.h, res["spins"]))
+
+
+def test_budget_rejects_oversized_request(nmfa):
+    inst = instances.sk(500, 1)
+    with nmfa.Server(precision="bf16", hbm_budget_bytes=1 << 20) as srv:
+        t = srv.submit(inst.J, inst.h, 1024, 100, 1)
+        assert srv.wait(t, 60000)
+        assert srv.poll(t) == nmfa.NMFA_ENOMEM
+        with pytest.raises(nmfa.NmfaError):
+            srv.result(t)
+
+
+def test_cancel_queued_and_running(nmfa):
+    big = instances.sk(200, 2)
+    with nmfa.Server(precision="bf16", max_active=1, chunk_iters=50) as srv:
+        t1 = srv.submit(big.J, big.h, 4096, 5000, 1)
+        t2 = srv.submit(big.J, big.h, 64, 100, 2)
+        srv.cancel(t2)  # still queued behind t1 (max_active = 1)
+        assert srv.poll(t2) == nmfa.NMFA_ECANCELED
+        time.sleep(0.1)
+        srv.cancel(t1)
+        assert srv.wait(t1, 60000)
+        assert srv.poll(t1) == nmfa.NMFA_ECANCELED
+        t3 = srv.submit(big.J, big.h, 64, 100, 3)
+        assert srv.wait(t3, 60000) and srv.poll(t3) == nmfa.JOB_DONE

@@ -1,0 +1,112 @@
+"""GPU parity of the persistent XCD-group kernel (large N, BF16 / FP8-J operands).
+
+Bars:
+* early trajectory (first 10 iterations) within 5e-3 of the FP64 oracle (BF16 operand rounding
+  of states of order 0.1), energies of the returned spins bit-exact;
+* the XCD-local and the device-fenced exchange give bit-identical states (same arithmetic);
+* replica-prefix and checkpoint/resume invariance are bit-exact;
+* at the full benchmark size (N=2000, R=1024, t_f=5000) the kernel runs in XCD-local mode,
+  sampled replicas follow the oracle for the first iterations and all energies are exact;
+* on a K2000-class instance (complete graph, J = +-1, N=2000) the success probability at the FP64
+  path's 10th-percentile energy is within 2 binomial standard errors of the FP64 path's.
+"""
+import numpy as np
+import pytest
+
+import instances
+import oracle
+from oracle import stats
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nmfa():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_08422_amd import nmfa as m
+
+    return m
+
+
+def _early_traj_check(nmfa, inst, precision, R, t_f, seed, sub, n_rec=10, **kw):
+    with nmfa.Solver(inst.J, inst.h, precision=precision, record_iters=n_rec, **kw) as s:
+        s.anneal(R, t_f, seed)
+        traj = s.trajectory()
+        spins = s.spins()
+        E, Ei = s.energies()
+        path = s.info()["path"]
+    _, _, otraj = oracle.anneal(inst.J, inst.h, oracle.schedule(t_f)[:n_rec], replicas=sub, seed=seed,
+                                record=n_rec)
+    err = np.max(np.abs(traj[:, sub, :] - otraj))
+    return path, err, spins, E, Ei
+
+
+@pytest.mark.parametrize("n,R,precision", [(200, 300, "bf16"), (333, 130, "fp8j_bf16s"),
+                                           (1000, 129, "bf16"), (70, 40, "fp8j_bf16s")])
+def test_xcd_early_trajectory_and_energies(nmfa, n, R, precision):
+    inst = instances.sk(n, 3)
+    inst.h = np.round(instances.gaussian_fields(n, 1.0, 2))
+    sub = [0, R // 2, R - 1]
+    path, err, spins, E, Ei = _early_traj_check(nmfa, inst, precision, R, 400, 17, sub, force_xcd=True)
+    assert path in ("xcd", "xcd_fenced")
+    assert err <= 5e-3, err
+    assert np.array_equal(Ei, oracle.energies_int(inst.J, inst.h, spins))
+
+
+def test_xcd_local_and_fenced_exchange_agree(nmfa):
+    """P = 4 workgroups per group, 64 groups: 256 workgroups, every XCD holds whole groups."""
+    inst = instances.gnp(200, 0.3, 5)
+    R, t_f = 64 * 128, 300
+    out = {}
+    for fenced in (False, True):
+        with nmfa.Solver(inst.J, inst.h, precision="bf16", force_xcd=True, force_fenced=fenced) as s:
+            s.anneal(R, t_f, 99)
+            out[fenced] = (s.state(), s.info()["path"])
+    assert out[False][1] == "xcd" and out[True][1] == "xcd_fenced"
+    assert np.array_equal(out[False][0], out[True][0])
+
+
+def test_xcd_replica_prefix_and_resume(nmfa):
+    inst = instances.sk(300, 8)
+    t_f, seed = 250, 4
+    with nmfa.Solver(inst.J, inst.h, precision="bf16", force_xcd=True) as s:
+        s.anneal(400, t_f, seed)
+        full400 = s.state()
+        s.anneal(150, t_f, seed)
+        full150 = s.state()
+        s.anneal_range(150, t_f, 1, 97, seed)
+        s.anneal_range(150, t_f, 98, t_f, seed)
+        resumed = s.state()
+    assert np.array_equal(full400[:150], full150)
+    assert np.array_equal(resumed, full150)
+
+
+def test_full_size_benchmark_configuration(nmfa):
+    """G(2000, 0.5), R=1024, t_f=5000, FP8-J / BF16-S: the launch configuration the benchmark times."""
+    inst = instances.gnp(2000, 0.5, 1)
+    R, t_f, seed = 1024, 5000, 1000
+    sub = [0, 511, 1023]
+    path, err, spins, E, Ei = _early_traj_check(nmfa, inst, "fp8j_bf16s", R, t_f, seed, sub, n_rec=5)
+    assert path == "xcd"
+    assert err <= 5e-3, err
+    rows = np.arange(0, R, 97)
+    assert np.array_equal(Ei[rows], oracle.energies_int(inst.J, inst.h, spins[rows]))
+
+
+def test_k2000_class_success_vs_fp64(nmfa):
+    inst = instances.sk(2000, 4)  # complete graph with +-1 couplings (the K2000 class)
+    R, t_f = 1024, 5000
+    with nmfa.Solver(inst.J, inst.h, precision="fp64") as s:
+        s.anneal(R, t_f, 2024)
+        E64 = s.energies()[0]
+    with nmfa.Solver(inst.J, inst.h, precision="fp8j_bf16s") as s:
+        s.anneal(R, t_f, 2025)
+        E16 = s.energies()[0]
+        assert s.info()["path"] == "xcd"
+    target = float(np.percentile(E64, 10))
+    p64 = stats.success_probability(E64, target)
+    p16 = stats.success_probability(E16, target)
+    assert stats.within_two_se(p16, R, p64, R), (p16, p64)

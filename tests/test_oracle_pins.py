@@ -346,3 +346,19 @@ def test_tts99():
     assert stats.tts99(2.0, 0.995) == 2.0
     # p = 0.9: ln(0.01)/ln(0.1) = 2 samples
     assert stats.tts99(3.0, 0.9) == pytest.approx(6.0)
+
+
+def test_uniform_mode_two_cycle_closed_form():
+    """Complete graph J = 1, uniform field h = 0.5, sigma = 0, T = 1e-4 (saturated tanh): all spins
+    share m_t with m_{t+1} = (1 - alpha) m_t - alpha sign(h + (n-1) m_t), which converges to the
+    2-cycle -alpha/(2-alpha) (odd t) <-> +alpha/(2-alpha) (even t). This is the period-2
+    instability of the uniform mode that dense antiferromagnetic instances fall into."""
+    n, alpha, t_f = 50, 0.15, 200
+    J = np.ones((n, n)) - np.eye(n)
+    h = np.full(n, 0.5)
+    _, _, traj = oracle.anneal(J, h, np.full(t_f, 1e-4), R=1, seed=1, alpha=alpha, sigma=0.0,
+                               record=t_f)
+    amp = alpha / (2 - alpha)
+    assert traj[0, 0, 0] == -alpha  # first step: -alpha * sign(h)
+    assert np.allclose(traj[-1], amp, rtol=0, atol=1e-12)      # t = 200 (even)
+    assert np.allclose(traj[-2], -amp, rtol=0, atol=1e-12)     # t = 199 (odd)
