@@ -247,26 +247,40 @@ def main() -> int:
 
     extra = {}
     if not args.no_extra:
-        # FP64 GPU path on the same workload: the 5x comparator and the TTS99 target
+        # FP64 GPU path on the same workload: the 5x comparator
         with nmfa.Solver(inst.J, inst.h, precision="fp64") as s64:
             walls, tms = timed_anneals(s64, R, T_F, [77], stream)
-            E64, _ = s64.energies()
         ms64 = walls[0]
-        E_target = float(np.percentile(E64, 10))
-        p16 = float(np.mean(E16 <= E_target))
-        p64 = float(np.mean(E64 <= E_target))
         extra["fp64_path"] = {
             "ms_per_anneal": ms64,
             "spin_updates_per_s": spin_updates / (ms64 * 1e-3),
             "speedup_of_headline": (spin_updates / (ms_per_step * 1e-3)) / (spin_updates / (ms64 * 1e-3)),
         }
-        extra["tts99_n2000"] = {
-            "E_target": E_target, "target_rule": "10th percentile of the FP64 path's energies",
-            "p_headline": p16, "p_fp64": p64,
-            "tts99_s_headline": tts99(ms_per_step * 1e-3 / R, p16),
-            "tts99_s_fp64": tts99(ms64 * 1e-3 / R, p64),
-            "max_cut_best_headline": float((np.triu(inst.J, 1).sum() - E16.min()) / 2),
+        # Solution quality at N = 2000. On G(2000, 1/2) every sample of the method collapses into the
+        # uniform period-2 mode (cut 0, for FP64 as well), so TTS99 is quoted on the K2000 class
+        # (complete graph, J = +-1) with the same kernels: target = 10th-percentile energy of an
+        # independent FP64 run.
+        k2 = instances.sk(N, 2000)
+        with nmfa.Solver(k2.J, k2.h, precision="fp64") as s64:
+            s64.anneal(R, T_F, 3001, stream)
+            E_ref = s64.energies()[0]
+            w64, _ = timed_anneals(s64, R, T_F, [3002], stream)
+            E64 = s64.energies()[0]
+        with nmfa.Solver(k2.J, k2.h, precision="fp8j_bf16s") as s16:
+            w16, _ = timed_anneals(s16, R, T_F, [3003], stream)
+            Ek = s16.energies()[0]
+        E_target = float(np.percentile(E_ref, 10))
+        p16 = float(np.mean(Ek <= E_target))
+        p64 = float(np.mean(E64 <= E_target))
+        se = math.sqrt(p16 * (1 - p16) / R + p64 * (1 - p64) / R)
+        extra["tts99_n2000_k2000_class"] = {
+            "E_target": E_target, "target_rule": "10th percentile of an independent FP64 run",
+            "p_fp8j_bf16s": p16, "p_fp64": p64, "z_diff": (p16 - p64) / se if se > 0 else 0.0,
+            "tts99_s_fp8j_bf16s": tts99(w16[0] * 1e-3 / R, p16),
+            "tts99_s_fp64": tts99(w64[0] * 1e-3 / R, p64),
+            "mean_E_fp8j_bf16s": float(Ek.mean()), "mean_E_fp64": float(E64.mean()),
         }
+        extra["g2000_cut_best_headline"] = float((np.triu(inst.J, 1).sum() - E16.min()) / 2)
         # N = 100 workloads: dense SK (BF16, R=16384) and dense MAX-CUT (the paper's timing case)
         sk = instances.sk(100, 1)
         with nmfa.Solver(sk.J, sk.h, precision="bf16") as sb, nmfa.Solver(sk.J, sk.h, precision="fp64") as sd:

@@ -96,6 +96,21 @@ static uint8_t fp8e4m3_bits(double v) {
   return sign | (uint8_t)((ex + 7) << 3) | (uint8_t)f;
 }
 
+static double fp8e4m3_value(uint8_t b) {
+  const int e = (b >> 3) & 0xf, m = b & 7;
+  double w = (e == 0) ? std::ldexp((double)m, -9) : std::ldexp(1.0 + m / 8.0, e - 7);
+  return (b & 0x80) ? -w : w;
+}
+
+// FP4 E2M1 code (sign bit 8, magnitudes 0, 1/2, 1, 3/2, 2, 3, 4, 6) of v, or -1 if v is not one.
+static int fp4e2m1_code(double v) {
+  static const double mags[8] = {0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0};
+  const double a = std::fabs(v);
+  for (int k = 0; k < 8; ++k)
+    if (a == mags[k]) return (v < 0 ? 8 : 0) | k;
+  return -1;
+}
+
 static bool is_integral(double v) { return std::isfinite(v) && v == std::floor(v) && std::fabs(v) < 9e15; }
 
 // ------------------------------------------------------------------------------------------
@@ -255,30 +270,32 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   // kernel path and padded layout
   const size_t es = c->op_size();
   const bool bf = (c->prec == NMFA_BF16 || c->prec == NMFA_FP8J_BF16S);
-  bool j_fp8_exact = true;  // every coupling is exactly an FP8 E4M3 value
-  for (size_t k = 0; k < nn && j_fp8_exact; ++k) {
-    const uint8_t b = fp8e4m3_bits(Jf[k]);
-    const int e = (b >> 3) & 0xf, m = b & 7;
-    double w = (e == 0) ? std::ldexp((double)m, -9) : std::ldexp(1.0 + m / 8.0, e - 7);
-    if (b & 0x80) w = -w;
-    if (w != Jf[k]) j_fp8_exact = false;
+  // exact formats of the couplings the MFMA consumes (FP8-rounded for the FP8-J precision)
+  bool j_fp8_exact = true, j_fp4_exact = true;
+  for (size_t k = 0; k < nn && (j_fp8_exact || j_fp4_exact); ++k) {
+    const double v = (c->prec == NMFA_FP8J_BF16S) ? fp8e4m3_value(fp8e4m3_bits(Jf[k])) : Jf[k];
+    if (c->prec != NMFA_FP8J_BF16S && fp8e4m3_value(fp8e4m3_bits(v)) != v) j_fp8_exact = false;
+    if (fp4e2m1_code(v) < 0) j_fp4_exact = false;
   }
   const int Mp_s = (int)round_up(n, 16);
   const int Kp_s = (int)round_up(n, bf ? 32 : 16);
   const int stride_s = (int)((round_up(Kp_s * es, 256) + 16) / es);
   const bool small_fits = Mp_s <= 256 && small_lds_bytes(c->prec, Mp_s, stride_s) <= (size_t)device_max_lds();
-  // persistent XCD-group kernel: BF16 operands, J rows in LDS as BF16 or (exact / FP8-J) FP8
+  // persistent XCD-group kernel: BF16 operands; J rows in LDS as FP4 / FP8 when exact, else BF16
   const int Mp_x = (int)round_up(n, xcd_rows());
   const int Kp_x = (int)round_up(n, 128);
-  const bool x_j8 = (c->prec == NMFA_FP8J_BF16S) || (Kp_x > 1024 && j_fp8_exact);
-  const bool x_ok = bf && Mp_x / xcd_rows() <= 32 && (x_j8 || Kp_x <= 1024) &&
-                    xcd_lds_bytes(x_j8, Kp_x) <= (size_t)device_max_lds();
+  const int x_jfmt = j_fp4_exact ? 2 : (j_fp8_exact ? 1 : 0);
+  const size_t x_jlds = xcd_j_lds_bytes(x_jfmt, Kp_x);
+  const long x_room = (long)device_max_lds() - (long)x_jlds;
+  const int x_nbuf = (int)std::min<long>(6, x_room > 0 ? x_room / (long)xcd_chunk_bytes() : 0);
+  const bool x_ok = bf && Mp_x / xcd_rows() <= 32 && x_nbuf >= 2;
   if (p->flags & NMFA_FLAG_FORCE_STEP) {
     c->path = 1;
   } else if ((p->flags & NMFA_FLAG_FORCE_XCD) && x_ok) {
     c->path = 2;
   } else if ((p->flags & NMFA_FLAG_FORCE_XCD)) {
-    return fail(NMFA_EINVAL, "nmfa_create: the XCD-group kernel needs BF16 / FP8-J precision and n <= 2048");
+    return fail(NMFA_EINVAL, "nmfa_create: the XCD-group kernel needs BF16 / FP8-J precision, n <= 2048 and "
+                             "couplings that fit its LDS");
   } else if (small_fits) {
     c->path = 0;
   } else if (x_ok) {
@@ -294,7 +311,8 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->Mp = Mp_x;
     c->Kp = Kp_x;
     c->lds_stride = 0;
-    c->j_fp8 = x_j8;
+    c->jfmt = x_jfmt;
+    c->nbuf = x_nbuf;
   } else {
     c->Mp = (int)round_up(n, 64);
     c->Kp = c->Mp;
@@ -313,31 +331,32 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     hterm[i] = (c->prec == NMFA_FP64) ? hi : hi * inv[i];
   }
 
-  // operand copy of J: FP8 bytes for the FP8-J kernels, else the precision's operand type
-  const bool j8_store = (c->prec == NMFA_FP8J_BF16S && c->path == 0) || (c->path == 2 && c->j_fp8);
-  const size_t jbytes = (size_t)Mp * Kp * (j8_store ? 1 : es);
+  // operand copy of J: FP8 bytes for the small FP8-J kernel; FP4 / FP8 / BF16 for the XCD-group
+  // kernel; else the precision's operand type (FP8-J on the per-iteration path: FP8-rounded BF16)
+  const bool j8_small = (c->prec == NMFA_FP8J_BF16S && c->path == 0);
+  const int jfmt2 = (c->path == 2) ? c->jfmt : -1;
+  size_t jbytes;
+  if (j8_small || jfmt2 == 1) jbytes = (size_t)Mp * Kp;
+  else if (jfmt2 == 2) jbytes = (size_t)Mp * Kp / 2;
+  else jbytes = (size_t)Mp * Kp * (jfmt2 == 0 ? 2 : es);
   std::vector<unsigned char> jbuf(jbytes, 0);
   for (int i = 0; i < n; ++i) {
     for (int j = 0; j < n; ++j) {
-      const double v = Jf[(size_t)i * n + j];
+      double v = Jf[(size_t)i * n + j];
+      if (c->prec == NMFA_FP8J_BF16S) v = fp8e4m3_value(fp8e4m3_bits(v));
       const size_t idx = (size_t)i * Kp + j;
-      if (j8_store) {
+      if (j8_small || jfmt2 == 1) {
         jbuf[idx] = fp8e4m3_bits(v);
+      } else if (jfmt2 == 2) {
+        const uint8_t code = (uint8_t)fp4e2m1_code(v);
+        jbuf[idx / 2] |= (uint8_t)((idx & 1) ? (code << 4) : code);
       } else if (c->prec == NMFA_FP64) {
         std::memcpy(&jbuf[idx * 8], &v, 8);
       } else if (c->prec == NMFA_FP32) {
         const float f = (float)v;
         std::memcpy(&jbuf[idx * 4], &f, 4);
       } else {
-        // BF16, and FP8 J on the per-iteration path: FP8-rounded values widened to BF16
-        double w = v;
-        if (c->prec == NMFA_FP8J_BF16S) {
-          const uint8_t b = fp8e4m3_bits(v);
-          const int e = (b >> 3) & 0xf, m = b & 7;
-          w = (e == 0) ? std::ldexp((double)m, -9) : std::ldexp(1.0 + m / 8.0, e - 7);
-          if (b & 0x80) w = -w;
-        }
-        const uint16_t bits = bf16_bits(w);
+        const uint16_t bits = bf16_bits(v);
         std::memcpy(&jbuf[idx * 2], &bits, 2);
       }
     }
@@ -417,6 +436,9 @@ static int ensure_run_buffers(nmfa_ctx* c, int R) {
     const size_t sb = (size_t)Rp * c->Kp * c->op_size();
     HIP_TRY(hipMalloc(&c->d_S[0], sb));
     HIP_TRY(hipMalloc(&c->d_S[1], sb));
+    // columns beyond the padded rows are read (times zero couplings) but never written
+    HIP_TRY(hipMemset(c->d_S[0], 0, sb));
+    HIP_TRY(hipMemset(c->d_S[1], 0, sb));
     c->cap_Rp = Rp;
   }
   return NMFA_OK;
@@ -556,7 +578,8 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
       x.P = P;
       x.group_base = gb;
       x.force_fenced = (c->flags & NMFA_FLAG_FORCE_FENCED) ? 1 : 0;
-      HIP_TRY(launch_anneal_xcd(c->j_fp8, a, x, ng, st));
+      x.nbuf = c->nbuf;
+      HIP_TRY(launch_anneal_xcd(c->jfmt, a, x, ng, st));
       ++c->launches;
     }
     HIP_TRY(hipEventRecord(c->evm, st));

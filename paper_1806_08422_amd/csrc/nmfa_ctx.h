@@ -14,7 +14,8 @@ struct nmfa_ctx {
   int n = 0;
   int prec = NMFA_BF16;
   int path = 0;  // 0 = persistent small-N kernel, 1 = per-iteration kernel, 2 = XCD-group kernel
-  bool j_fp8 = false;        // path 2: J rows held as FP8 in LDS
+  int jfmt = 1;              // path 2: J format in LDS (0 BF16, 1 FP8 E4M3, 2 FP4 E2M1)
+  int nbuf = 2;              // path 2: spin chunk buffers in LDS
   unsigned* d_ctl = nullptr; // path 2: control block
   bool ctl_pending = false;  // path 2: abort/mode flags not yet read back
   int exchange_mode = 0;     // path 2: 1 = XCD-local, 2 = device-scope fences

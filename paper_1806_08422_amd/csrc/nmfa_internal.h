@@ -33,14 +33,17 @@ struct XcdArgs {
   int P;             // workgroups per replica group = Mp / xcd_rows()
   int group_base;    // first replica group of this launch
   int force_fenced;  // test hook: use device-scope fences even when the groups are XCD-local
+  int nbuf;          // spin chunk buffers in LDS (2..6)
 };
 
 hipError_t launch_anneal_small(int prec, const AnnealArgs& a, hipStream_t st);
 // jobs: device array of AnnealArgs (one per job); tasks: device array of (job, replica block).
 hipError_t launch_anneal_small_batched(int prec, const AnnealArgs* jobs, const int2* tasks, int n_tasks,
                                        int max_Mp, size_t lds, hipStream_t st);
-hipError_t launch_anneal_xcd(bool j_fp8, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
-size_t xcd_lds_bytes(bool j_fp8, int Kp);
+// jfmt: format of J in global memory and LDS: 0 = BF16, 1 = FP8 E4M3, 2 = FP4 E2M1
+hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
+size_t xcd_j_lds_bytes(int jfmt, int Kp);
+size_t xcd_chunk_bytes();
 int xcd_ctl_words();
 int xcd_rows();
 int xcd_group_replicas();

@@ -291,6 +291,7 @@ void scheduler(nmfa_server* s) {
     for (Job* j : ran) {
       const size_t k = std::find(round_jobs.begin(), round_jobs.end(), j) - round_jobs.begin();
       j->t_done = t_end_of[k];
+      j->ctx->state_valid = true;  // the next round resumes from this state
     }
     for (Job* j : done) {
       j->E.resize(j->R);

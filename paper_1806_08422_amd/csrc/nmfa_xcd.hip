@@ -5,15 +5,18 @@
 // own 64 rows of J; after each iteration the group exchanges its new spins through memory and
 // meets at a barrier.
 //
-//   * J: the workgroup's 64 rows stay in LDS for the whole anneal (FP8 E4M3, or BF16 when it
-//     fits), 8/16-byte chunks XOR-swizzled by row so that the A-fragment reads are conflict free.
+//   * J: the workgroup's 64 rows stay in LDS for the whole anneal, in the narrowest format that
+//     holds them exactly: FP4 E2M1 (couplings in {0, +-1/2, +-1, +-3/2, +-2, +-3, +-4, +-6}), FP8
+//     E4M3, or BF16; chunks of 8 values XOR-swizzled by row so the A-fragment reads are conflict
+//     free. Every format is widened to BF16 in registers for the MFMA.
 //   * S: the operand copy (BF16) of the group's spins lives in global memory, double-buffered by
 //     iteration parity, layout [replica][Kp]. Each iteration the workgroup streams it through
-//     LDS in chunks of 64 k with the direct-to-LDS loads of gfx950 (global_load_lds_dwordx4),
-//     double-buffered so the next chunk loads while the MFMAs consume the current one.
-//   * Wave (a, b) of the 4 waves computes 32 rows (two 16-row tiles) x 64 replicas (four 16-column
-//     tiles) with v_mfma_f32_16x16x32_bf16; FP8 J is widened to BF16 in registers
-//     (v_cvt_scalef32_pk_bf16_fp8, one A fragment reused for four MFMAs).
+//     LDS in chunks of 64 k (16 KB) with the direct-to-LDS loads of gfx950
+//     (global_load_lds_dwordx4) in a ring of up to 6 buffers, so up to 5 chunks are in flight
+//     while the MFMAs consume the oldest one (the L2 latency is hidden only with that many bytes
+//     in flight; the buffers are what the LDS left after J allows).
+//   * Wave (a, b) of the 8 waves (two per SIMD, so one hides the other's LDS latency) computes 32
+//     rows (two 16-row tiles) x 32 replicas (two 16-column tiles) with v_mfma_f32_16x16x32_bf16.
 //   * The epilogue (normalisation, Philox noise, tanh, damped update) runs in registers on the
 //     accumulator layout; the FP32 master state never leaves the registers between iterations.
 //   * Barrier: the P workgroups of a group count arrivals with a device-scope atomic and poll it
@@ -63,14 +66,48 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16x8(uint32_t lo, uint32_t hi) {
   return r;
 }
 
-template <bool J_FP8>
-__global__ __launch_bounds__(256, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
-  extern __shared__ __align__(16) unsigned char smem[];  // all of LDS: J rows + S chunks
-  constexpr int JES = J_FP8 ? 1 : 2;  // bytes per J element in LDS
-  const int N = a.N, Kp = a.Kp, P = x.P;
+// Widen 8 FP4 E2M1 values (one 32-bit word, value 2b in the low nibble of byte b) to 8 BF16.
+__device__ __forceinline__ bf16x8 fp4x8_to_bf16x8(uint32_t w) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 0);
+  const bf16x2 p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 1);
+  const bf16x2 p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 2);
+  const bf16x2 p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 3);
+  bf16x8 r;
+  r[0] = p0[0]; r[1] = p0[1]; r[2] = p1[0]; r[3] = p1[1];
+  r[4] = p2[0]; r[5] = p2[1]; r[6] = p3[0]; r[7] = p3[1];
+  return r;
+}
+
+// Wait until at most n of this wave's vector-memory loads are outstanding (n <= 15; LDS and
+// export counters are not waited on).
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(0xF70 | 0); break;
+    case 2: __builtin_amdgcn_s_waitcnt(0xF70 | 2); break;
+    case 4: __builtin_amdgcn_s_waitcnt(0xF70 | 4); break;
+    case 6: __builtin_amdgcn_s_waitcnt(0xF70 | 6); break;
+    default: __builtin_amdgcn_s_waitcnt(0xF70 | 8); break;
+  }
+}
+
+// Workgroup barrier without the memory fence of __syncthreads (which would also wait for the
+// chunks still in flight); the asm statements keep the compiler from moving LDS accesses across.
+__device__ __forceinline__ void bare_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// JFMT: 0 = BF16, 1 = FP8 E4M3, 2 = FP4 E2M1 (format of J in global memory and in LDS)
+template <int JFMT>
+__global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
+  extern __shared__ __align__(16) unsigned char smem[];  // all of LDS: J rows + S chunk ring
+  const int N = a.N, Kp = a.Kp, P = x.P, nbuf = x.nbuf;
+  const int jrow = JFMT == 0 ? Kp * 2 : (JFMT == 1 ? Kp : Kp / 2);  // bytes of one J row
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g4 = lane >> 4, c = lane & 15;
-  const int wa = wave >> 1, wb = wave & 1;  // rows 32*wa.., replicas 64*wb..
+  const int wa = wave >> 2, wb = wave & 3;  // rows 32*wa.., replicas 32*wb..
   unsigned* ctl = x.ctl;
 
   // ---- registration: find the XCD of every workgroup, then agree on the mapping -------------
@@ -107,24 +144,22 @@ __global__ __launch_bounds__(256, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
   const bool xcd_mode = ld_dev(&ctl[CTL_WG + 4 * blockIdx.x + 2]) != 0;
   bool aborted = ld_dev(&ctl[CTL_ABORT]) != 0;
 
-  // ---- LDS: J rows (swizzled), two S chunk buffers ----------------------------------------
-  unsigned char* Jl = smem;                              // [64][Kp * JES]
-  unsigned char* Sl = smem + (size_t)XCD_ROWS * Kp * JES;  // [2][128][64] bf16
+  // ---- LDS: J rows (swizzled), ring of S chunk buffers -----------------------------------
+  unsigned char* Jl = smem;                           // [64][jrow]
+  unsigned char* Sl = smem + (size_t)XCD_ROWS * jrow;  // [nbuf][128][64] bf16
   {
-    // J chunks: 8 bytes (FP8) or 16 bytes (BF16); swizzle chunk index with the row
-    const int chunk_bytes = J_FP8 ? 8 : 16;
-    const int chunks_per_row = Kp * JES / chunk_bytes;
-    const unsigned char* Jg = reinterpret_cast<const unsigned char*>(a.J) + (size_t)rb * XCD_ROWS * Kp * JES;
-    for (int idx = tid; idx < XCD_ROWS * chunks_per_row; idx += 256) {
+    // chunks of 8 values: 16 bytes (BF16), 8 (FP8) or 4 (FP4); XOR-swizzled with the row
+    constexpr int cb = JFMT == 0 ? 16 : (JFMT == 1 ? 8 : 4);
+    const int chunks_per_row = Kp / 8;
+    const unsigned char* Jg = reinterpret_cast<const unsigned char*>(a.J) + (size_t)rb * XCD_ROWS * jrow;
+    for (int idx = tid; idx < XCD_ROWS * chunks_per_row; idx += blockDim.x) {
       const int row = idx / chunks_per_row, ch = idx - row * chunks_per_row;
-      const int sw = J_FP8 ? (ch ^ (row & 15)) : (ch ^ (row & 7));
-      if (J_FP8) {
-        *reinterpret_cast<uint2*>(Jl + (size_t)row * Kp + sw * 8) =
-            *reinterpret_cast<const uint2*>(Jg + (size_t)row * Kp + ch * 8);
-      } else {
-        *reinterpret_cast<uint4*>(Jl + (size_t)row * Kp * 2 + sw * 16) =
-            *reinterpret_cast<const uint4*>(Jg + (size_t)row * Kp * 2 + ch * 16);
-      }
+      const int sw = JFMT == 0 ? (ch ^ (row & 7)) : (ch ^ (row & 15));
+      unsigned char* dst = Jl + (size_t)row * jrow + sw * cb;
+      const unsigned char* src = Jg + (size_t)row * jrow + ch * cb;
+      if (JFMT == 0) *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+      else if (JFMT == 1) *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(src);
+      else *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(src);
     }
   }
 
@@ -134,7 +169,7 @@ __global__ __launch_bounds__(256, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
   float* state = reinterpret_cast<float*>(a.state);
   float* traj = reinterpret_cast<float*>(a.traj);
   const float* coef = reinterpret_cast<const float*>(a.coef);
-  float inv[2][4], hv[2][4], s[2][4][4];
+  float inv[2][4], hv[2][4], s[2][2][4];
   int row0[2];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt) {
@@ -145,9 +180,9 @@ __global__ __launch_bounds__(256, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
       hv[rt][v] = h_g[row0[rt] + v];
     }
   }
-  const int rgroup0 = group * XCD_RG + 64 * wb;  // first replica of this wave
+  const int rgroup0 = group * XCD_RG + 32 * wb;  // first replica of this wave
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
+  for (int ct = 0; ct < 2; ++ct) {
     const int r = rgroup0 + 16 * ct + c;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -174,13 +209,13 @@ __global__ __launch_bounds__(256, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
     const __bf16* Sgrp = Scur + (size_t)group * XCD_RG * Kp;
 
     // DMA of one chunk: 128 replicas x 64 k (16 KB) = 16 wave-instructions of 1 KB; wave w issues
-    // replica blocks 4w..4w+3 (8 replicas each). Lane l fills LDS position (l/8, l%8) of its block
+    // replica blocks 2w, 2w+1 (8 replicas each). Lane l fills LDS position (l/8, l%8) of its block
     // with global column (l%8) ^ (replica & 7).
     auto issue_chunk = [&](int ch, int buf) {
       unsigned char* dst = Sl + (size_t)buf * XCD_RG * XCD_KC * 2;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int blk = 4 * wave + u;
+      for (int u = 0; u < 2; ++u) {
+        const int blk = 2 * wave + u;
         const int rep = blk * 8 + (lane >> 3);
         const int col = (lane & 7) ^ (rep & 7);
         const __bf16* src = Sgrp + (size_t)rep * Kp + ch * XCD_KC + col * 8;
@@ -188,55 +223,65 @@ __global__ __launch_bounds__(256, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
       }
     };
 
-    f32x4 acc[2][4];
+    f32x4 acc[2][2];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
+      for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
 
-    issue_chunk(0, 0);
+    const int prologue = min(nbuf - 1, nchunks);
+    for (int q = 0; q < prologue; ++q) issue_chunk(q, q);
+    int buf = 0;
     for (int ch = 0; ch < nchunks; ++ch) {
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's DMA of chunk ch has landed
-      __syncthreads();               // ... and every wave's; buffer (ch+1)&1 is free again
-      if (ch + 1 < nchunks) issue_chunk(ch + 1, (ch + 1) & 1);
-      const unsigned char* Sb = Sl + (size_t)(ch & 1) * XCD_RG * XCD_KC * 2;
+      wait_vm(2 * min(nbuf - 2, nchunks - 1 - ch));  // this wave's part of chunk ch has landed
+      bare_barrier();                                // ... every wave's; chunk ch-1's buffer is free
+      const int nxt = ch + nbuf - 1;
+      if (nxt < nchunks) issue_chunk(nxt, buf == 0 ? nbuf - 1 : buf - 1);
+      const unsigned char* Sb = Sl + (size_t)buf * XCD_RG * XCD_KC * 2;
+      buf = (buf + 1 == nbuf) ? 0 : buf + 1;
+      // all fragments of the chunk first, then the MFMAs
+      bf16x8 af[2][2], bfr[2][2];
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        const int kk = ch * XCD_KC + 32 * ks + 8 * g4;  // k of this lane group within Kp
-        bf16x8 af[2];
+        const int chunk8 = ((ch * XCD_KC + 32 * ks) >> 3) + g4;  // 8-value chunk of this lane group
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
           const int lrow = 32 * wa + 16 * rt + c;
-          if (J_FP8) {
-            const int chunk = kk >> 3;
-            const int sw = (chunk & ~15) | ((chunk & 15) ^ (lrow & 15));
-            const uint2 raw = *reinterpret_cast<const uint2*>(Jl + (size_t)lrow * Kp + sw * 8);
-            af[rt] = fp8x8_to_bf16x8(raw.x, raw.y);
+          if (JFMT == 0) {
+            const int sw = (chunk8 & ~7) | ((chunk8 & 7) ^ (lrow & 7));
+            af[ks][rt] = *reinterpret_cast<const bf16x8*>(Jl + (size_t)lrow * jrow + sw * 16);
+          } else if (JFMT == 1) {
+            const int sw = (chunk8 & ~15) | ((chunk8 & 15) ^ (lrow & 15));
+            const uint2 raw = *reinterpret_cast<const uint2*>(Jl + (size_t)lrow * jrow + sw * 8);
+            af[ks][rt] = fp8x8_to_bf16x8(raw.x, raw.y);
           } else {
-            const int chunk = kk >> 3;
-            const int sw = (chunk & ~7) | ((chunk & 7) ^ (lrow & 7));
-            af[rt] = *reinterpret_cast<const bf16x8*>(Jl + (size_t)lrow * Kp * 2 + sw * 16);
+            const int sw = (chunk8 & ~15) | ((chunk8 & 15) ^ (lrow & 15));
+            af[ks][rt] = fp4x8_to_bf16x8(*reinterpret_cast<const uint32_t*>(Jl + (size_t)lrow * jrow + sw * 4));
           }
         }
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-          const int rep = 64 * wb + 16 * ct + c;
+        for (int ct = 0; ct < 2; ++ct) {
+          const int rep = 32 * wb + 16 * ct + c;
           const int col = (4 * ks + g4) ^ (rep & 7);
-          const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(Sb + (size_t)rep * 128 + col * 16);
-#pragma unroll
-          for (int rt = 0; rt < 2; ++rt)
-            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rt], bfr, acc[rt][ct], 0, 0, 0);
+          bfr[ks][ct] = *reinterpret_cast<const bf16x8*>(Sb + (size_t)rep * 128 + col * 16);
         }
       }
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][rt], bfr[ks][ct], acc[rt][ct], 0, 0, 0);
     }
 
     // ---- fused epilogue --------------------------------------------------------------------
     const float coef_t = coef[t - 1];
     const int k_rec = t - a.t_begin;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
+    for (int ct = 0; ct < 2; ++ct) {
       const int r = rgroup0 + 16 * ct + c;
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
@@ -289,7 +334,7 @@ __global__ __launch_bounds__(256, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
 
   // ---- final state and readout ---------------------------------------------------------------
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
+  for (int ct = 0; ct < 2; ++ct) {
     const int r = rgroup0 + 16 * ct + c;
     if (r >= a.R) continue;
 #pragma unroll
@@ -305,24 +350,26 @@ __global__ __launch_bounds__(256, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
   }
 }
 
-size_t xcd_lds_bytes(bool j_fp8, int Kp) {
-  return (size_t)XCD_ROWS * Kp * (j_fp8 ? 1 : 2) + 2 * (size_t)XCD_RG * XCD_KC * 2;
+size_t xcd_j_lds_bytes(int jfmt, int Kp) {
+  return (size_t)XCD_ROWS * (jfmt == 0 ? (size_t)Kp * 2 : (jfmt == 1 ? (size_t)Kp : (size_t)Kp / 2));
 }
+size_t xcd_chunk_bytes() { return (size_t)XCD_RG * XCD_KC * 2; }
 
 int xcd_ctl_words() { return CTL_WORDS; }
 int xcd_rows() { return XCD_ROWS; }
 int xcd_group_replicas() { return XCD_RG; }
 int xcd_chunk() { return XCD_KC; }
 
-hipError_t launch_anneal_xcd(bool j_fp8, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
-  const size_t lds = xcd_lds_bytes(j_fp8, a.Kp);
-  const void* fn = j_fp8 ? (const void*)anneal_xcd<true> : (const void*)anneal_xcd<false>;
+hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
+  const size_t lds = xcd_j_lds_bytes(jfmt, a.Kp) + (size_t)x.nbuf * xcd_chunk_bytes();
+  const void* fn = jfmt == 0 ? (const void*)anneal_xcd<0> : (jfmt == 1 ? (const void*)anneal_xcd<1>
+                                                                       : (const void*)anneal_xcd<2>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   AnnealArgs aa = a;
   XcdArgs xx = x;
   void* args[] = {&aa, &xx};
-  return hipLaunchCooperativeKernel(fn, dim3(groups * x.P), dim3(256), args, lds, st);
+  return hipLaunchCooperativeKernel(fn, dim3(groups * x.P), dim3(512), args, lds, st);
 }
 
 }  // namespace nmfa

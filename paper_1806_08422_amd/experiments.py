@@ -1,0 +1,149 @@
+"""The paper's experiments, re-run in form on synthetic stand-in instances (library API only).
+
+The paper's instance sets, figure data and Gset graphs are not available, so these reproduce the
+*shape* of each experiment on seeded synthetic instances of the same classes and sizes; nothing
+here compares against the paper's numbers.
+
+* ``fig3``  -- Sec. II, Fig. 3: a 16-spin Moebius ladder with the schedule compressed to 100
+  iterations; per-iteration spin values of one sample and the Ising energy of their signs.
+* ``fig4``  -- Sec. III, Fig. 4: success probability and time to solution (99%) against N for
+  SK (J = +-1), dense MAX-CUT (p = 1/2) and degree-3 MAX-CUT instances (10, 10 and 20 instances
+  per size), 10,000 samples per instance. The success target of an instance is the best energy
+  seen in any of its samples.
+* ``table1`` -- Table I: mean and best MAX-CUT value over 100 runs on 2000-spin instances: a
+  random graph with 19,990 unit edges (the G22 class), a scale-free Barabasi-Albert graph with
+  about 12,000 unit edges (the G39 class) and a complete graph with +-1 weights (K2000 class).
+
+Usage: python -m paper_1806_08422_amd.experiments {fig3,fig4,table1} [--out FILE.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import instances  # noqa: E402
+from paper_1806_08422_amd import nmfa  # noqa: E402
+
+
+def _energy_of_signs(J, h, s):
+    sp = np.where(s >= 0, 1.0, -1.0)
+    return 0.5 * np.einsum("ri,ij,rj->r", sp, J, sp) + (0.0 if h is None else sp @ h)
+
+
+def fig3(seed: int = 3, t_f: int = 100):
+    inst = instances.moebius_ladder(16)
+    with nmfa.Solver(inst.J, inst.h, precision="fp64", record_iters=t_f) as s:
+        s.anneal(1, t_f, seed)
+        traj = s.trajectory()[:, 0, :]  # [t, spin]
+    energies = _energy_of_signs(inst.J, None, traj)
+    return {"instance": "moebius ladder, 16 spins", "t_f": t_f, "spins": traj.tolist(),
+            "energy_of_signs": energies.tolist(), "ground_energy_closed_form": -20}
+
+
+def _tts99(t_sample, p):
+    if p <= 0:
+        return math.inf
+    if p >= 0.99:
+        return t_sample
+    return t_sample * math.log(0.01) / math.log(1 - p)
+
+
+def fig4(sizes=(20, 40, 60, 80, 100), samples=10000, t_f=1000, precision="bf16"):
+    classes = {
+        "sk": (10, lambda n, k: instances.sk(n, 100 + k)),
+        "dense_maxcut": (10, lambda n, k: instances.gnp(n, 0.5, 200 + k)),
+        "degree3_maxcut": (20, lambda n, k: instances.random_regular(n, 3, 300 + k)),
+    }
+    out = {}
+    for name, (count, make) in classes.items():
+        rows = []
+        for n in sizes:
+            ps, tts = [], []
+            for k in range(count):
+                inst = make(n, k)
+                with nmfa.Solver(inst.J, inst.h, precision=precision) as s:
+                    t0 = time.perf_counter()
+                    s.anneal(samples, t_f, 5000 + k)
+                    E = s.energies()[0]
+                    dt = time.perf_counter() - t0
+                p = float(np.mean(E <= E.min()))
+                ps.append(p)
+                tts.append(_tts99(dt / samples, p))
+            rows.append({"n": n, "success_median": float(np.median(ps)),
+                         "success_iqr": [float(np.percentile(ps, 25)), float(np.percentile(ps, 75))],
+                         "tts99_median_s": float(np.median(tts))})
+        out[name] = rows
+    return {"samples_per_instance": samples, "t_f": t_f, "precision": precision, "classes": out}
+
+
+def _ba_graph(n, m, seed):
+    import networkx as nx
+
+    g = nx.barabasi_albert_graph(n, m, seed=seed)
+    J = np.zeros((n, n))
+    for a, b in g.edges():
+        J[a, b] = J[b, a] = 1.0
+    return J
+
+
+def _random_graph_m(n, m, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    J = np.zeros((n, n))
+    edges = set()
+    while len(edges) < m:
+        a, b = rng.integers(0, n, size=2)
+        if a != b:
+            edges.add((min(a, b), max(a, b)))
+    for a, b in edges:
+        J[a, b] = J[b, a] = 1.0
+    return J
+
+
+def table1(runs=100, t_f=5000, precision="fp8j_bf16s"):
+    cases = {
+        "random (G22 class)": _random_graph_m(2000, 19990, 22),
+        "scale-free (G39 class)": _ba_graph(2000, 6, 39),
+        "fully connected +-1 (K2000 class)": instances.sk(2000, 2000).J,
+    }
+    out = {}
+    for name, J in cases.items():
+        with nmfa.Solver(J, None, precision=precision) as s:
+            s.anneal(runs, t_f, 777)
+            cuts = s.cuts()
+            path = s.info()["path"]
+        out[name] = {"mean_cut": float(cuts.mean()), "best_cut": float(cuts.max()), "runs": runs,
+                     "edges_weight": float(np.triu(J, 1).sum()), "kernel_path": path}
+    return {"t_f": t_f, "precision": precision, "instances": out}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("experiment", choices=["fig3", "fig4", "table1"])
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--samples", type=int, default=10000)
+    args = ap.parse_args(argv)
+    if args.experiment == "fig3":
+        res = fig3()
+    elif args.experiment == "fig4":
+        res = fig4(samples=args.samples)
+    else:
+        res = table1()
+    text = json.dumps(res)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text[:2000])
+
+
+if __name__ == "__main__":
+    main()

@@ -87,15 +87,20 @@ def test_budget_rejects_oversized_request(nmfa):
 
 
 def test_cancel_queued_and_running(nmfa):
-    big = instances.sk(200, 2)
-    with nmfa.Server(precision="bf16", max_active=1, chunk_iters=50) as srv:
-        t1 = srv.submit(big.J, big.h, 4096, 5000, 1)
-        t2 = srv.submit(big.J, big.h, 64, 100, 2)
+    big = instances.sk(2000, 2)
+    small = instances.sk(200, 2)
+    with nmfa.Server(precision="bf16", max_active=1, chunk_iters=20) as srv:
+        t1 = srv.submit(big.J, big.h, 4096, 5000, 1)    # hundreds of rounds
+        t2 = srv.submit(small.J, small.h, 64, 100, 2)
         srv.cancel(t2)  # still queued behind t1 (max_active = 1)
         assert srv.poll(t2) == nmfa.NMFA_ECANCELED
-        time.sleep(0.1)
+        deadline = time.time() + 60
+        while srv.poll(t1) == nmfa.JOB_QUEUED and time.time() < deadline:
+            time.sleep(0.001)
+        assert srv.poll(t1) == nmfa.JOB_RUNNING
         srv.cancel(t1)
         assert srv.wait(t1, 60000)
         assert srv.poll(t1) == nmfa.NMFA_ECANCELED
-        t3 = srv.submit(big.J, big.h, 64, 100, 3)
+        t3 = srv.submit(small.J, small.h, 64, 100, 3)
         assert srv.wait(t3, 60000) and srv.poll(t3) == nmfa.JOB_DONE
+        assert srv.stats()["cancelled"] == 2
