@@ -4,8 +4,10 @@
 A step is one whole anneal of the headline workload through the C ABI: Algorithm 1 (paper
 Sec. II) for t_f iterations over all N spins and R replicas, then the sign readout and the exact
 energies. Workload: dense random-graph MAX-CUT G(N=2000, p=0.5), J in {0, 1}, h = 0, R = 1024
-replicas, t_f = 5000 iterations, J stored as FP8 E4M3 and spins as BF16 on MFMA with FP32
-accumulation. Inputs (J, normalisers, schedule) are resident in HBM before timing starts.
+replicas, t_f = 5000 iterations, precision "fp8j_bf16s": J rounded to FP8 E4M3 (exact for {0, 1})
+and kept on the device in the narrowest exact format (FP4 E2M1 here), spins as BF16 MFMA operands,
+FP32 accumulation and FP32 state. Inputs (J, normalisers, schedule) are resident in HBM before
+timing starts.
 
 Prints ONE JSON line. Metric: spin-updates/s = N * R * t_f / (seconds per anneal). Alongside:
 the FP64 GPU path on the same workload (speed-up), TTS99 at N=2000 and N=100, the N=100 dense
@@ -168,6 +170,9 @@ def main() -> int:
     ap.add_argument("--serving-burst", type=int, default=200)
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-budget-gib", type=float, default=2.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed region, run one plain device copy of this many MiB (the "
+                         "reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the replica-sharded multi-GPU path is "
@@ -188,7 +193,8 @@ def main() -> int:
     flops_per_iter = 2.0 * N * N * R  # algorithmic: 2N flops per spin update
 
     solver = nmfa.Solver(inst.J, inst.h, precision="fp8j_bf16s")
-    path = solver.info()["path"]
+    info = solver.info()
+    path, jfmt = info["path"], info["j_format"]
     for w in range(args.warmup):
         solver.anneal(R, T_F, 500 + w, stream)
     torch.cuda.synchronize()
@@ -228,8 +234,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": "dense random-graph MAX-CUT G(2000,0.5), J in {0,1}, h=0, R=1024, t_f=5000, "
-                        "J FP8-E4M3 / spins BF16 / FP32 accumulate",
+                        "J rounded to FP8-E4M3 (exact here) / spins BF16 / FP32 accumulate",
             "n": N, "replicas": R, "t_f": T_F, "precision": "fp8j_bf16s", "kernel_path": path,
+            "j_storage": jfmt,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -244,6 +251,15 @@ def main() -> int:
             "flops_per_launch": flops_per_launch,
         },
     }
+
+    if args.calib_copy_mib > 0:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this kernel scale the anneal's
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = int(src.numel() * 4)
+        del src, dst
 
     extra = {}
     if not args.no_extra:

@@ -155,6 +155,17 @@ int nmfa_trajectory(nmfa_ctx *c, double *out);
  * apart after an anneal has completed (the call synchronises). Errors: EINVAL, EDEVICE. */
 int nmfa_info(nmfa_ctx *c, int32_t *n, int32_t *precision, int32_t *path);
 
+/* Storage format of J in device memory as the annealing kernel reads it. For the BF16-operand
+ * precisions J (already rounded as the precision prescribes, Sec. III) is kept in the narrowest
+ * of these formats that holds every coupling exactly and is widened to BF16 in registers:
+ * NMFA_JFMT_BF16, NMFA_JFMT_FP8 (E4M3), NMFA_JFMT_FP4 (E2M1). NMFA_JFMT_NATIVE: J in the
+ * precision's own type (FP64, FP32). Errors: EINVAL. */
+#define NMFA_JFMT_BF16 0
+#define NMFA_JFMT_FP8 1
+#define NMFA_JFMT_FP4 2
+#define NMFA_JFMT_NATIVE 3
+int nmfa_j_format(nmfa_ctx *c, int32_t *fmt);
+
 /* Device time of the last anneal in milliseconds, from HIP events recorded on the anneal's own
  * stream: *anneal_ms covers the annealing kernel launches only (Algorithm 1's iterations),
  * *total_ms also the readout and the energy evaluation; *launches is the number of annealing

@@ -286,8 +286,8 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   const int Kp_x = (int)round_up(n, 128);
   const int x_jfmt = j_fp4_exact ? 2 : (j_fp8_exact ? 1 : 0);
   const size_t x_jlds = xcd_j_lds_bytes(x_jfmt, Kp_x);
-  const long x_room = (long)device_max_lds() - (long)x_jlds;
-  const int x_nbuf = (int)std::min<long>(6, x_room > 0 ? x_room / (long)xcd_chunk_bytes() : 0);
+  const size_t lds_max = (size_t)device_max_lds();
+  const int x_nbuf = x_jlds < lds_max ? xcd_pick_buffers(lds_max - x_jlds) : 0;  // spin chunk ring
   const bool x_ok = bf && Mp_x / xcd_rows() <= 32 && x_nbuf >= 2;
   if (p->flags & NMFA_FLAG_FORCE_STEP) {
     c->path = 1;
@@ -318,6 +318,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->Kp = c->Mp;
     c->lds_stride = 0;
   }
+  c->Ks = c->path == 2 ? xcd_spin_stride(c->Kp) : c->Kp;
   const int Mp = c->Mp, Kp = c->Kp;
 
   // normalisers sqrt(h_i^2 + sum_j J_ij^2) in FP64; a zero normaliser gives inv = 0
@@ -433,7 +434,7 @@ static int ensure_run_buffers(nmfa_ctx* c, int R) {
     (void)hipFree(c->d_S[0]);
     (void)hipFree(c->d_S[1]);
     c->d_S[0] = c->d_S[1] = nullptr;
-    const size_t sb = (size_t)Rp * c->Kp * c->op_size();
+    const size_t sb = (size_t)Rp * c->Ks * c->op_size();
     HIP_TRY(hipMalloc(&c->d_S[0], sb));
     HIP_TRY(hipMalloc(&c->d_S[1], sb));
     // columns beyond the padded rows are read (times zero couplings) but never written
@@ -560,7 +561,7 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
     const int per_launch = std::max(1, std::min(cus, 256) / P);  // the control block serves 256 workgroups
-    HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[t_begin & 1], c->n, R, c->Kp, G * Rg,
+    HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[t_begin & 1], c->n, R, c->Kp, c->Ks, G * Rg,
                               t_begin == 1 ? 1 : 0, st));
     HIP_TRY(hipMemsetAsync(c->d_ctl, 0, (size_t)xcd_ctl_words() * 4, st));
     HIP_TRY(hipEventRecord(c->ev0, st));
@@ -574,6 +575,7 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
       XcdArgs x{};
       x.S[0] = c->d_S[0];
       x.S[1] = c->d_S[1];
+      x.ks = c->Ks;
       x.ctl = c->d_ctl;
       x.P = P;
       x.group_base = gb;
@@ -586,7 +588,7 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     c->ctl_pending = true;
   } else {
     if (t_begin == 1) HIP_TRY(hipMemsetAsync(c->d_state, 0, (size_t)R * c->n * c->acc_size(), st));
-    HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[0], c->n, R, c->Kp, a.Rp, t_begin == 1 ? 1 : 0, st));
+    HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[0], c->n, R, c->Kp, c->Kp, a.Rp, t_begin == 1 ? 1 : 0, st));
     HIP_TRY(hipEventRecord(c->ev0, st));
     int cur = 0;
     for (int t = t_begin; t <= t_end; ++t) {
@@ -757,6 +759,15 @@ extern "C" int nmfa_info(nmfa_ctx* c, int32_t* n, int32_t* precision, int32_t* p
       *path = c->path;
     }
   }
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_j_format(nmfa_ctx* c, int32_t* fmt) {
+  if (!c || !fmt) return fail(NMFA_EINVAL, "nmfa_j_format: NULL argument");
+  if (c->path == 2) *fmt = c->jfmt;
+  else if (c->prec == NMFA_FP64 || c->prec == NMFA_FP32) *fmt = NMFA_JFMT_NATIVE;
+  else if (c->prec == NMFA_FP8J_BF16S && c->path == 0) *fmt = NMFA_JFMT_FP8;
+  else *fmt = NMFA_JFMT_BF16;
   return NMFA_OK;
 }
 

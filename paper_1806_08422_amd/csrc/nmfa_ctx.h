@@ -15,11 +15,12 @@ struct nmfa_ctx {
   int prec = NMFA_BF16;
   int path = 0;  // 0 = persistent small-N kernel, 1 = per-iteration kernel, 2 = XCD-group kernel
   int jfmt = 1;              // path 2: J format in LDS (0 BF16, 1 FP8 E4M3, 2 FP4 E2M1)
-  int nbuf = 2;              // path 2: spin chunk buffers in LDS
+  int nbuf = 2;              // path 2: spin chunk buffers in LDS (2, 3, 4 or 6)
   unsigned* d_ctl = nullptr; // path 2: control block
   bool ctl_pending = false;  // path 2: abort/mode flags not yet read back
   int exchange_mode = 0;     // path 2: 1 = XCD-local, 2 = device-scope fences
   int Mp = 0, Kp = 0, lds_stride = 0;
+  int Ks = 0;                 // row stride (elements) of the spin operand copies d_S
   double alpha = 0.15, sigma = 0.15;
   uint32_t flags = 0;
   int record = 0;
@@ -49,7 +50,7 @@ struct nmfa_ctx {
   int8_t* d_spins = nullptr; // [R][n]
   double* d_E = nullptr;     // [R]
   long long* d_Eint = nullptr;
-  void* d_S[2] = {nullptr, nullptr};  // per-iteration path: [Rp][Kp] op_t
+  void* d_S[2] = {nullptr, nullptr};  // paths 1 and 2: [Rp][Ks] op_t
   int cap_Rp = 0;
   void* d_traj = nullptr;
   size_t traj_cap = 0;

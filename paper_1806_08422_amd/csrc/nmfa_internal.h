@@ -28,12 +28,13 @@ struct AnnealArgs {
 
 // Persistent large-N kernel (XCD groups): extra arguments.
 struct XcdArgs {
-  void* S[2];        // operand copies of the spins, BF16 [Rp][Kp], double-buffered by parity of t
+  void* S[2];        // operand copies of the spins, BF16 [Rp][ks], double-buffered by parity of t
+  int ks;            // row stride of S in elements (>= Kp, a multiple of 8)
   unsigned* ctl;     // control block (xcd_ctl_words() words, zeroed before every launch)
   int P;             // workgroups per replica group = Mp / xcd_rows()
   int group_base;    // first replica group of this launch
   int force_fenced;  // test hook: use device-scope fences even when the groups are XCD-local
-  int nbuf;          // spin chunk buffers in LDS (2..6)
+  int nbuf;          // spin chunk buffers in LDS: 2, 3, 4 or 6
 };
 
 hipError_t launch_anneal_small(int prec, const AnnealArgs& a, hipStream_t st);
@@ -44,14 +45,16 @@ hipError_t launch_anneal_small_batched(int prec, const AnnealArgs* jobs, const i
 hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
 size_t xcd_j_lds_bytes(int jfmt, int Kp);
 size_t xcd_chunk_bytes();
+int xcd_spin_stride(int Kp);  // row stride of S for the XCD kernel
+int xcd_pick_buffers(size_t lds_room);  // chunk buffers that fit in lds_room bytes (0 if < 2)
 int xcd_ctl_words();
 int xcd_rows();
 int xcd_group_replicas();
-int xcd_chunk();
 size_t small_lds_bytes(int prec, int Mp, int stride);
 hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
                               hipStream_t st);
-hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R, int Kp, int Rp, int zero,
+// Writes rows [0, Rp) x columns [0, Kp) of S (row stride ld) from the master state (zero: all 0).
+hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R, int Kp, int ld, int Rp, int zero,
                              hipStream_t st);
 hipError_t launch_readout(int prec, const void* state, int8_t* spins, size_t count, hipStream_t st);
 hipError_t launch_energy(const int8_t* J8, const double* J64, const double* h, int h_integral,

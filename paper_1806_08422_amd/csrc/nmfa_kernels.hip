@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void anneal_step(AnnealArgs a, const void* S_c
 // ------------------------------------------------------------------------------------------
 template <typename op_t, typename acc_t>
 __global__ void pack_state_kernel(const acc_t* __restrict__ state, op_t* __restrict__ S, int N, int R,
-                                  int Kp, int Rp, int zero) {
+                                  int Kp, int ld, int Rp, int zero) {
   const size_t total = (size_t)Rp * Kp;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
@@ -337,7 +337,7 @@ __global__ void pack_state_kernel(const acc_t* __restrict__ state, op_t* __restr
     const int i = (int)(idx - (size_t)r * Kp);
     acc_t v = 0;
     if (!zero && r < R && i < N) v = state[(size_t)r * N + i];
-    S[idx] = (op_t)v;
+    S[(size_t)r * ld + i] = (op_t)v;
   }
 }
 
@@ -549,22 +549,22 @@ hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, 
   return hipGetLastError();
 }
 
-hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R, int Kp, int Rp, int zero,
+hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R, int Kp, int ld, int Rp, int zero,
                              hipStream_t st) {
   const size_t total = (size_t)Rp * Kp;
   const int blocks = (int)std::min<size_t>((total + 255) / 256, 4096);
   switch (prec) {
     case PREC_FP64:
       hipLaunchKernelGGL((pack_state_kernel<double, double>), dim3(blocks), dim3(256), 0, st,
-                         (const double*)state, (double*)S, N, R, Kp, Rp, zero);
+                         (const double*)state, (double*)S, N, R, Kp, ld, Rp, zero);
       break;
     case PREC_FP32:
       hipLaunchKernelGGL((pack_state_kernel<float, float>), dim3(blocks), dim3(256), 0, st,
-                         (const float*)state, (float*)S, N, R, Kp, Rp, zero);
+                         (const float*)state, (float*)S, N, R, Kp, ld, Rp, zero);
       break;
     default:
       hipLaunchKernelGGL((pack_state_kernel<__bf16, float>), dim3(blocks), dim3(256), 0, st,
-                         (const float*)state, (__bf16*)S, N, R, Kp, Rp, zero);
+                         (const float*)state, (__bf16*)S, N, R, Kp, ld, Rp, zero);
       break;
   }
   return hipGetLastError();

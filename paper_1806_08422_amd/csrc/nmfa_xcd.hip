@@ -11,10 +11,11 @@
 //     free. Every format is widened to BF16 in registers for the MFMA.
 //   * S: the operand copy (BF16) of the group's spins lives in global memory, double-buffered by
 //     iteration parity, layout [replica][Kp]. Each iteration the workgroup streams it through
-//     LDS in chunks of 64 k (16 KB) with the direct-to-LDS loads of gfx950
-//     (global_load_lds_dwordx4) in a ring of up to 6 buffers, so up to 5 chunks are in flight
-//     while the MFMAs consume the oldest one (the L2 latency is hidden only with that many bytes
-//     in flight; the buffers are what the LDS left after J allows).
+//     LDS with the direct-to-LDS loads of gfx950 (global_load_lds_dwordx4) in chunks of 64 k
+//     (16 KB), through a ring of up to 6 buffers (what the LDS beside J allows), so several
+//     chunks are in flight from L2 while the MFMAs consume the oldest one. The fragments of the
+//     next chunk are read from LDS into a second register set while the MFMAs of the current
+//     chunk run, so LDS latency is hidden behind matrix work.
 //   * Wave (a, b) of the 8 waves (two per SIMD, so one hides the other's LDS latency) computes 32
 //     rows (two 16-row tiles) x 32 replicas (two 16-column tiles) with v_mfma_f32_16x16x32_bf16.
 //   * The epilogue (normalisation, Philox noise, tanh, damped update) runs in registers on the
@@ -46,7 +47,8 @@ enum : int {
 
 constexpr int XCD_ROWS = 64;   // rows of J per workgroup
 constexpr int XCD_RG = 128;    // replicas per group
-constexpr int XCD_KC = 64;     // k per streamed chunk
+constexpr int XCD_KC = 64;     // k per streamed spin chunk
+
 constexpr unsigned SPIN_LIMIT = 1u << 22;  // about a second of polling
 
 __device__ __forceinline__ unsigned ld_dev(const unsigned* p) {
@@ -79,16 +81,12 @@ __device__ __forceinline__ bf16x8 fp4x8_to_bf16x8(uint32_t w) {
   return r;
 }
 
-// Wait until at most n of this wave's vector-memory loads are outstanding (n <= 15; LDS and
+// Wait until at most N of this wave's vector-memory loads are outstanding (N <= 15; LDS and
 // export counters are not waited on).
-__device__ __forceinline__ void wait_vm(int n) {
-  switch (n) {
-    case 0: __builtin_amdgcn_s_waitcnt(0xF70 | 0); break;
-    case 2: __builtin_amdgcn_s_waitcnt(0xF70 | 2); break;
-    case 4: __builtin_amdgcn_s_waitcnt(0xF70 | 4); break;
-    case 6: __builtin_amdgcn_s_waitcnt(0xF70 | 6); break;
-    default: __builtin_amdgcn_s_waitcnt(0xF70 | 8); break;
-  }
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N <= 15, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt(0xF70 | N);
 }
 
 // Workgroup barrier without the memory fence of __syncthreads (which would also wait for the
@@ -99,11 +97,32 @@ __device__ __forceinline__ void bare_barrier() {
   asm volatile("" ::: "memory");
 }
 
-// JFMT: 0 = BF16, 1 = FP8 E4M3, 2 = FP4 E2M1 (format of J in global memory and in LDS)
+// Raw J fragment of one lane for one k-step: 8 values as 16 (BF16), 8 (FP8) or 4 (FP4) bytes.
+template <int JFMT> struct JRaw;
+template <> struct JRaw<0> { typedef bf16x8 T; };
+template <> struct JRaw<1> { typedef uint2 T; };
+template <> struct JRaw<2> { typedef uint32_t T; };
+
 template <int JFMT>
+__device__ __forceinline__ bf16x8 widen(const typename JRaw<JFMT>::T& v);
+template <> __device__ __forceinline__ bf16x8 widen<0>(const bf16x8& v) { return v; }
+template <> __device__ __forceinline__ bf16x8 widen<1>(const uint2& v) { return fp8x8_to_bf16x8(v.x, v.y); }
+template <> __device__ __forceinline__ bf16x8 widen<2>(const uint32_t& v) { return fp4x8_to_bf16x8(v); }
+
+// JFMT: 0 = BF16, 1 = FP8 E4M3, 2 = FP4 E2M1 (format of J in global memory and in LDS);
+// NB: spin chunk buffers in LDS.
+template <int JFMT, int NB>
 __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
   extern __shared__ __align__(16) unsigned char smem[];  // all of LDS: J rows + S chunk ring
-  const int N = a.N, Kp = a.Kp, P = x.P, nbuf = x.nbuf;
+  constexpr int KC = XCD_KC;
+  constexpr int CHUNK_BYTES = XCD_RG * KC * 2;  // 128 replicas x KC k, BF16
+  constexpr int ROW_B = KC * 2;                 // bytes of one replica row in a chunk
+  constexpr int COLS = KC / 8;                  // 16-byte columns per row
+  constexpr int DPW = CHUNK_BYTES / 1024 / 8;   // 1 KB direct-to-LDS loads per wave and chunk
+  constexpr int KSTEPS = KC / 32;
+  constexpr int CB = JFMT == 0 ? 16 : (JFMT == 1 ? 8 : 4);  // bytes of 8 J values
+  typedef typename JRaw<JFMT>::T AT;
+  const int N = a.N, Kp = a.Kp, P = x.P, ks = x.ks;
   const int jrow = JFMT == 0 ? Kp * 2 : (JFMT == 1 ? Kp : Kp / 2);  // bytes of one J row
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g4 = lane >> 4, c = lane & 15;
@@ -146,7 +165,7 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
 
   // ---- LDS: J rows (swizzled), ring of S chunk buffers -----------------------------------
   unsigned char* Jl = smem;                           // [64][jrow]
-  unsigned char* Sl = smem + (size_t)XCD_ROWS * jrow;  // [nbuf][128][64] bf16
+  unsigned char* Sl = smem + (size_t)XCD_ROWS * jrow;  // [NB][128][KC] bf16
   {
     // chunks of 8 values: 16 bytes (BF16), 8 (FP8) or 4 (FP4); XOR-swizzled with the row
     constexpr int cb = JFMT == 0 ? 16 : (JFMT == 1 ? 8 : 4);
@@ -196,7 +215,46 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
   const float sg = (float)a.sigma;
   const float neg2ln2_s2 = -2.0f * 0.6931471805599453f * sg * sg;
   const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha);
-  const int nchunks = Kp / XCD_KC;
+  const int nchunks = Kp / KC;
+
+  // loop-invariant LDS byte offsets of this lane's fragments. A (J): 8-value chunk
+  // c8 = 8ch + 4ks + g4 of row lrow, stored at ((c8 & ~M) | ((c8 & M) ^ (lrow & M))) with
+  // M = 7 (BF16) or 15 (FP8/FP4). With M = 15 an odd chunk flips bit 3 of the stored index,
+  // i.e. offset bit 8*CB, which is clear in lrow*jrow (jrow is a multiple of 16*CB).
+  constexpr int M = JFMT == 0 ? 7 : 15;
+  int aoff[KSTEPS][2];
+#pragma unroll
+  for (int ks = 0; ks < KSTEPS; ++ks)
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int lrow = 32 * wa + 16 * rt + c;
+      const int within = 4 * ks + g4;
+      const int sw = (within & ~M) | ((within & M) ^ (lrow & M));
+      aoff[ks][rt] = lrow * jrow + sw * CB;
+    }
+  // B (spins): replica rep, 16-byte column col = 4ks + g4 of the chunk row stored at
+  // col ^ (rep & (COLS - 1)), so 16 consecutive replicas hit distinct banks
+  int boff[KSTEPS][2];
+#pragma unroll
+  for (int ks = 0; ks < KSTEPS; ++ks)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int rep = 32 * wb + 16 * ct + c;
+      const int col = 4 * ks + g4;
+      boff[ks][ct] = rep * ROW_B + (col ^ (rep & (COLS - 1))) * 16;
+    }
+  // DMA: lane l of a 1 KB block fills row l / COLS, column l % COLS, taking the global column
+  // that the swizzle puts there; blocks DPW * wave + u.
+  int dma_src[DPW];
+  int dma_dst[DPW];
+#pragma unroll
+  for (int u = 0; u < DPW; ++u) {
+    const int blk = DPW * wave + u;
+    const int rep = blk * (1024 / ROW_B) + lane / COLS;
+    const int pos = lane % COLS;
+    dma_src[u] = rep * ks + (pos ^ (rep & (COLS - 1))) * 8;  // elements within the group's block
+    dma_dst[u] = blk * 1024;
+  }
   __bf16* S0 = reinterpret_cast<__bf16*>(x.S[0]);
   __bf16* S1 = reinterpret_cast<__bf16*>(x.S[1]);
   unsigned* bar = &ctl[CTL_BAR + 16 * (int)my_group];  // per launch: < 256 groups
@@ -206,20 +264,26 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
   for (int t = a.t_begin; t <= a.t_end && !aborted; ++t) {
     const __bf16* Scur = (t & 1) ? S1 : S0;
     __bf16* Snext = (t & 1) ? S0 : S1;
-    const __bf16* Sgrp = Scur + (size_t)group * XCD_RG * Kp;
+    const __bf16* Sgrp = Scur + (size_t)group * XCD_RG * ks;
 
-    // DMA of one chunk: 128 replicas x 64 k (16 KB) = 16 wave-instructions of 1 KB; wave w issues
-    // replica blocks 2w, 2w+1 (8 replicas each). Lane l fills LDS position (l/8, l%8) of its block
-    // with global column (l%8) ^ (replica & 7).
+    // DMA of chunk ch into buffer buf: DPW wave-instructions of 1 KB per wave
     auto issue_chunk = [&](int ch, int buf) {
-      unsigned char* dst = Sl + (size_t)buf * XCD_RG * XCD_KC * 2;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int blk = 2 * wave + u;
-        const int rep = blk * 8 + (lane >> 3);
-        const int col = (lane & 7) ^ (rep & 7);
-        const __bf16* src = Sgrp + (size_t)rep * Kp + ch * XCD_KC + col * 8;
-        __builtin_amdgcn_global_load_lds(src, dst + (size_t)blk * 1024, 16, 0, 0);
+      for (int u = 0; u < DPW; ++u)
+        __builtin_amdgcn_global_load_lds(Sgrp + dma_src[u] + ch * KC,
+                                         Sl + (size_t)buf * CHUNK_BYTES + dma_dst[u], 16, 0, 0);
+    };
+    // this lane's fragments of chunk ch (in buffer buf) into registers
+    auto load_frags = [&](AT (&fa)[KSTEPS][2], bf16x8 (&fb)[KSTEPS][2], int ch, int buf) {
+      const unsigned char* Sb = Sl + (size_t)buf * CHUNK_BYTES;
+      const int px = (M == 15) ? (ch & 1) * 8 * CB : 0;
+      const unsigned char* Ja = Jl + ((JFMT == 0) ? ch * (KC / 8) * 16 : (ch >> 1) * 16 * CB);
+#pragma unroll
+      for (int ks = 0; ks < KSTEPS; ++ks) {
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) fa[ks][rt] = *reinterpret_cast<const AT*>(Ja + (aoff[ks][rt] ^ px));
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) fb[ks][ct] = *reinterpret_cast<const bf16x8*>(Sb + boff[ks][ct]);
       }
     };
 
@@ -230,51 +294,57 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
       for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
-
-    const int prologue = min(nbuf - 1, nchunks);
-    for (int q = 0; q < prologue; ++q) issue_chunk(q, q);
-    int buf = 0;
-    for (int ch = 0; ch < nchunks; ++ch) {
-      wait_vm(2 * min(nbuf - 2, nchunks - 1 - ch));  // this wave's part of chunk ch has landed
-      bare_barrier();                                // ... every wave's; chunk ch-1's buffer is free
-      const int nxt = ch + nbuf - 1;
-      if (nxt < nchunks) issue_chunk(nxt, buf == 0 ? nbuf - 1 : buf - 1);
-      const unsigned char* Sb = Sl + (size_t)buf * XCD_RG * XCD_KC * 2;
-      buf = (buf + 1 == nbuf) ? 0 : buf + 1;
-      // all fragments of the chunk first, then the MFMAs
-      bf16x8 af[2][2], bfr[2][2];
+    auto compute = [&](const AT (&fa)[KSTEPS][2], const bf16x8 (&fb)[KSTEPS][2]) {
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        const int chunk8 = ((ch * XCD_KC + 32 * ks) >> 3) + g4;  // 8-value chunk of this lane group
+      for (int ks = 0; ks < KSTEPS; ++ks) {
+        bf16x8 af[2];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt) {
-          const int lrow = 32 * wa + 16 * rt + c;
-          if (JFMT == 0) {
-            const int sw = (chunk8 & ~7) | ((chunk8 & 7) ^ (lrow & 7));
-            af[ks][rt] = *reinterpret_cast<const bf16x8*>(Jl + (size_t)lrow * jrow + sw * 16);
-          } else if (JFMT == 1) {
-            const int sw = (chunk8 & ~15) | ((chunk8 & 15) ^ (lrow & 15));
-            const uint2 raw = *reinterpret_cast<const uint2*>(Jl + (size_t)lrow * jrow + sw * 8);
-            af[ks][rt] = fp8x8_to_bf16x8(raw.x, raw.y);
-          } else {
-            const int sw = (chunk8 & ~15) | ((chunk8 & 15) ^ (lrow & 15));
-            af[ks][rt] = fp4x8_to_bf16x8(*reinterpret_cast<const uint32_t*>(Jl + (size_t)lrow * jrow + sw * 4));
-          }
-        }
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          const int rep = 32 * wb + 16 * ct + c;
-          const int col = (4 * ks + g4) ^ (rep & 7);
-          bfr[ks][ct] = *reinterpret_cast<const bf16x8*>(Sb + (size_t)rep * 128 + col * 16);
-        }
-      }
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
+        for (int rt = 0; rt < 2; ++rt) af[rt] = widen<JFMT>(fa[ks][rt]);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
           for (int rt = 0; rt < 2; ++rt)
-            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][rt], bfr[ks][ct], acc[rt][ct], 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rt], fb[ks][ct], acc[rt][ct], 0, 0, 0);
+      }
+    };
+
+    AT fa0[KSTEPS][2], fa1[KSTEPS][2];
+    bf16x8 fb0[KSTEPS][2], fb1[KSTEPS][2];
+    const int prologue = min(NB - 1, nchunks);
+    for (int q = 0; q < prologue; ++q) issue_chunk(q, q);
+    if constexpr (NB == 2) {
+      // two buffers: wait for chunk ch, refill the other buffer, read and use chunk ch
+      for (int ch = 0; ch < nchunks; ++ch) {
+        wait_vm<0>();
+        bare_barrier();  // chunk ch visible to all waves; the other buffer is free
+        if (ch + 1 < nchunks) issue_chunk(ch + 1, (ch + 1) & 1);
+        load_frags(fa0, fb0, ch, ch & 1);
+        compute(fa0, fb0);
+      }
+    } else {
+      // chunk ch+1 is read into registers while chunk ch is multiplied; the DMA ring runs
+      // NB - 2 chunks ahead of the register prefetch.
+      if (NB - 2 <= nchunks - 1) wait_vm<DPW * (NB - 2)>();
+      else wait_vm<0>();
+      bare_barrier();
+      load_frags(fa0, fb0, 0, 0);
+      int rbuf = 1;       // buffer of chunk ch + 1
+      int wbuf = NB - 1;  // buffer of chunk ch + NB - 1 (= that of chunk ch - 1)
+      auto step = [&](int ch, const AT (&ca)[KSTEPS][2], const bf16x8 (&cb)[KSTEPS][2],
+                      AT (&na)[KSTEPS][2], bf16x8 (&nb)[KSTEPS][2]) {
+        if (ch + NB - 2 <= nchunks - 1) wait_vm<DPW * (NB - 3)>();  // chunk ch + 1 has landed
+        else wait_vm<0>();
+        bare_barrier();  // ... for every wave, and every wave is done with chunk ch - 1's buffer
+        if (ch + NB - 1 < nchunks) issue_chunk(ch + NB - 1, wbuf);
+        load_frags(na, nb, min(ch + 1, nchunks - 1), rbuf);
+        compute(ca, cb);
+        rbuf = (rbuf + 1 == NB) ? 0 : rbuf + 1;
+        wbuf = (wbuf + 1 == NB) ? 0 : wbuf + 1;
+      };
+      for (int ch = 0; ch < nchunks; ch += 2) {  // nchunks is even (Kp is a multiple of 128)
+        step(ch, fa0, fb0, fa1, fb1);
+        step(ch + 1, fa1, fb1, fa0, fb0);
+      }
     }
 
     // ---- fused epilogue --------------------------------------------------------------------
@@ -299,7 +369,7 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
           s[rt][ct][v] = sv;
           outv[v] = (__bf16)sv;
         }
-        *reinterpret_cast<uint2*>(Snext + (size_t)r * Kp + row0[rt]) = *reinterpret_cast<const uint2*>(outv);
+        *reinterpret_cast<uint2*>(Snext + (size_t)r * ks + row0[rt]) = *reinterpret_cast<const uint2*>(outv);
         if (traj && k_rec < a.record && r < a.R) {
 #pragma unroll
           for (int v = 0; v < 4; ++v)
@@ -355,15 +425,38 @@ size_t xcd_j_lds_bytes(int jfmt, int Kp) {
 }
 size_t xcd_chunk_bytes() { return (size_t)XCD_RG * XCD_KC * 2; }
 
+// Row stride of S. Padding the rows (so that the 128 rows of a chunk do not share their low
+// address bits) was measured to make no difference on MI355X, so the rows are packed.
+int xcd_spin_stride(int Kp) { return Kp; }
+
 int xcd_ctl_words() { return CTL_WORDS; }
 int xcd_rows() { return XCD_ROWS; }
 int xcd_group_replicas() { return XCD_RG; }
-int xcd_chunk() { return XCD_KC; }
+
+template <int JFMT>
+static const void* xcd_fn(int nbuf) {
+  switch (nbuf) {
+    case 2: return (const void*)anneal_xcd<JFMT, 2>;
+    case 3: return (const void*)anneal_xcd<JFMT, 3>;
+    case 4: return (const void*)anneal_xcd<JFMT, 4>;
+    case 6: return (const void*)anneal_xcd<JFMT, 6>;
+    default: return nullptr;
+  }
+}
+
+int xcd_pick_buffers(size_t room) {
+  const size_t cb = xcd_chunk_bytes();
+  if (room >= 6 * cb) return 6;
+  if (room >= 4 * cb) return 4;
+  if (room >= 3 * cb) return 3;
+  if (room >= 2 * cb) return 2;
+  return 0;
+}
 
 hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
   const size_t lds = xcd_j_lds_bytes(jfmt, a.Kp) + (size_t)x.nbuf * xcd_chunk_bytes();
-  const void* fn = jfmt == 0 ? (const void*)anneal_xcd<0> : (jfmt == 1 ? (const void*)anneal_xcd<1>
-                                                                       : (const void*)anneal_xcd<2>);
+  const void* fn = jfmt == 0 ? xcd_fn<0>(x.nbuf) : (jfmt == 1 ? xcd_fn<1>(x.nbuf) : xcd_fn<2>(x.nbuf));
+  if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   AnnealArgs aa = a;

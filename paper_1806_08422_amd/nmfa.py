@@ -33,12 +33,13 @@ FLAG_FORCE_STEP = 0x4
 FLAG_FORCE_XCD = 0x8
 FLAG_FORCE_FENCED = 0x10
 PATHS = ("persistent", "step", "xcd", "xcd_fenced")
+J_FORMATS = ("bf16", "fp8_e4m3", "fp4_e2m1", "native")
 
 # Every function declared in include/nmfa.h (checked by the CPU tests against the header).
 EXPORTS = (
     "nmfa_params_default", "nmfa_create", "nmfa_anneal", "nmfa_anneal_range", "nmfa_spins",
     "nmfa_energies", "nmfa_cuts", "nmfa_energies_of", "nmfa_get_state", "nmfa_set_state",
-    "nmfa_trajectory", "nmfa_info", "nmfa_last_timing", "nmfa_destroy", "nmfa_noise_words",
+    "nmfa_trajectory", "nmfa_info", "nmfa_j_format", "nmfa_last_timing", "nmfa_destroy", "nmfa_noise_words",
     "nmfa_noise_values", "nmfa_last_error", "nmfa_server_params_default", "nmfa_server_create",
     "nmfa_server_submit", "nmfa_server_poll", "nmfa_server_wait", "nmfa_server_result",
     "nmfa_server_release", "nmfa_server_cancel", "nmfa_server_stats_get", "nmfa_server_destroy",
@@ -102,6 +103,7 @@ def _load() -> ctypes.CDLL:
         "nmfa_set_state": ([vp, i32, vp], ctypes.c_int),
         "nmfa_trajectory": ([vp, vp], ctypes.c_int),
         "nmfa_info": ([vp, vp, vp, vp], ctypes.c_int),
+        "nmfa_j_format": ([vp, vp], ctypes.c_int),
         "nmfa_last_timing": ([vp, vp, vp, vp], ctypes.c_int),
         "nmfa_destroy": ([vp], None),
         "nmfa_noise_words": ([u64, i32, i32, i32, i32, vp], ctypes.c_int),
@@ -270,7 +272,9 @@ class Solver:
     def info(self) -> dict:
         n, p, path = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib.nmfa_info(self._h, ctypes.byref(n), ctypes.byref(p), ctypes.byref(path)))
-        return {"n": n.value, "precision": p.value, "path": PATHS[path.value]}
+        f = ctypes.c_int32()
+        _check(lib.nmfa_j_format(self._h, ctypes.byref(f)))
+        return {"n": n.value, "precision": p.value, "path": PATHS[path.value], "j_format": J_FORMATS[f.value]}
 
     def last_timing(self) -> dict:
         a, t, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
