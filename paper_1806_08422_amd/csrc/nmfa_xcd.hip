@@ -462,7 +462,18 @@ hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, in
   AnnealArgs aa = a;
   XcdArgs xx = x;
   void* args[] = {&aa, &xx};
-  return hipLaunchCooperativeKernel(fn, dim3(groups * x.P), dim3(512), args, lds, st);
+  // Every workgroup of the launch must be resident at once (they wait for each other). One
+  // workgroup fills a CU's LDS, so that holds when the grid does not exceed the CU count; a
+  // launch that cannot become resident (a GPU shared with long-running work) ends in the bounded
+  // registration wait with an error rather than hanging. An ordinary launch is used rather than
+  // the cooperative-launch API, under which the ROCm profiler cannot trace the process.
+  int per_cu = 0, cus = 0, dev = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, lds);
+  if (e != hipSuccess) return e;
+  if ((long)per_cu * cus < (long)groups * x.P) return hipErrorCooperativeLaunchTooLarge;
+  return hipLaunchKernel(fn, dim3(groups * x.P), dim3(512), args, lds, st);
 }
 
 }  // namespace nmfa
