@@ -43,6 +43,24 @@ def tts99(t_sample_s: float, p: float) -> float:
     return t_sample_s * math.log(0.01) / math.log(1.0 - p)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the annealing kernel from the committed counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+
+    prof = os.path.join(ROOT, "profiles", "anneal_xcd_g2000_r1024_tf5000_hbm_bytes.md")
+    src = os.path.join(ROOT, "paper_1806_08422_amd", "csrc", "nmfa_xcd.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
+                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def timed_anneals(solver, R, t_f, seeds, stream):
     """Run one anneal per seed; return per-anneal wall ms (device-synchronised) and timings."""
     import torch
@@ -245,7 +263,7 @@ def main() -> int:
             "peak": PEAK_BF16_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_BF16_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic() if path == "xcd" else None,
             "kernel_avg_ms": kernel_ms,
             "launches_per_step": tm["launches"],
             "flops_per_launch": flops_per_launch,
