@@ -43,20 +43,20 @@ def tts99(t_sample_s: float, p: float) -> float:
     return t_sample_s * math.log(0.01) / math.log(1.0 - p)
 
 
-def measured_traffic():
+def measured_traffic(path: str):
     """HBM bytes per launch of the annealing kernel from the committed counter summary, or None
-    when the kernel source has changed since the counters were taken."""
+    when the kernel source has changed since the counters were taken (or another path ran)."""
     import hashlib
 
     prof = os.path.join(ROOT, "profiles", "anneal_xcd_g2000_r1024_tf5000_hbm_bytes.md")
     src = os.path.join(ROOT, "paper_1806_08422_amd", "csrc", "nmfa_xcd.hip")
     try:
         fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
-                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"))
+                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "kernel_path"))
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    if fields.get("kernel_source_sha256", "").strip() != sha:
+    if fields.get("kernel_source_sha256", "").strip() != sha or fields.get("kernel_path", "").strip() != path:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -263,7 +263,7 @@ def main() -> int:
             "peak": PEAK_BF16_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_BF16_TFLOPS,
-            "traffic": measured_traffic() if path == "xcd" else None,
+            "traffic": measured_traffic(path),
             "kernel_avg_ms": kernel_ms,
             "launches_per_step": tm["launches"],
             "flops_per_launch": flops_per_launch,

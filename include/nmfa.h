@@ -72,6 +72,8 @@ typedef enum nmfa_precision {
 #define NMFA_FLAG_FORCE_STEP 0x4u     /* use the per-iteration (large-N) kernel even if N is small */
 #define NMFA_FLAG_FORCE_XCD 0x8u      /* use the persistent XCD-group kernel (BF16 / FP8-J only) */
 #define NMFA_FLAG_FORCE_FENCED 0x10u  /* XCD-group kernel: exchange with device-scope fences */
+#define NMFA_FLAG_FORCE_LDS_J 0x20u   /* XCD-group kernel: keep J in LDS even where the
+                                         register-resident variant applies (test hook) */
 
 /* ---- parameters ------------------------------------------------------------------------------
  * Fill with nmfa_params_default() and override fields. struct_size must be sizeof(nmfa_params)
@@ -149,10 +151,12 @@ int nmfa_set_state(nmfa_ctx *c, int32_t R, const double *in);
 int nmfa_trajectory(nmfa_ctx *c, double *out);
 
 /* Information about a context: writes n, the precision and the kernel path (0 = persistent
- * small-N kernel with J in LDS; 1 = per-iteration kernel; 2 = persistent XCD-group kernel whose
- * groups exchanged spins through one XCD's L2; 3 = the same kernel with device-scope fences,
- * used when a group's workgroups were not all placed on one XCD). Paths 2/3 are only told
- * apart after an anneal has completed (the call synchronises). Errors: EINVAL, EDEVICE. */
+ * small-N kernel with J in LDS; 1 = per-iteration kernel; 2 = persistent XCD-group kernel with
+ * J rows in LDS whose groups exchanged spins through one XCD's L2; 3 = the same kernel with
+ * device-scope fences, used when a group's workgroups were not all placed on one XCD; 4 and 5 =
+ * the XCD-group kernel with J rows held in registers (FP4-exact couplings, n <= 2048), exchange
+ * as for 2 and 3). Paths 2/3 and 4/5 are only told apart after an anneal has completed (the call
+ * synchronises). Errors: EINVAL, EDEVICE. */
 int nmfa_info(nmfa_ctx *c, int32_t *n, int32_t *precision, int32_t *path);
 
 /* Storage format of J in device memory as the annealing kernel reads it. For the BF16-operand

@@ -289,6 +289,8 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   const size_t lds_max = (size_t)device_max_lds();
   const int x_nbuf = x_jlds < lds_max ? xcd_pick_buffers(lds_max - x_jlds) : 0;  // spin chunk ring
   const bool x_ok = bf && Mp_x / xcd_rows() <= 32 && x_nbuf >= 2;
+  // register-resident-J variant of the XCD-group kernel: FP4-exact couplings, n <= 2048
+  const bool x_rj = x_ok && x_jfmt == 2 && xrj_fits(n) && !(p->flags & NMFA_FLAG_FORCE_LDS_J);
   if (p->flags & NMFA_FLAG_FORCE_STEP) {
     c->path = 1;
   } else if ((p->flags & NMFA_FLAG_FORCE_XCD) && x_ok) {
@@ -307,6 +309,12 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->Mp = Mp_s;
     c->Kp = Kp_s;
     c->lds_stride = stride_s;
+  } else if (c->path == 2 && x_rj) {
+    c->xvar = 1;
+    c->Mp = (int)round_up(n, xrj_rows());
+    c->Kp = xrj_kp(n);
+    c->lds_stride = 0;
+    c->jfmt = x_jfmt;
   } else if (c->path == 2) {
     c->Mp = Mp_x;
     c->Kp = Kp_x;
@@ -555,9 +563,9 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     c->launches = 1;
     HIP_TRY(hipEventRecord(c->evm, st));
   } else if (c->path == 2) {
-    const int Rg = xcd_group_replicas();
+    const int Rg = c->xvar ? xrj_group_replicas() : xcd_group_replicas();
     const int G = (R + Rg - 1) / Rg;
-    const int P = c->Mp / xcd_rows();
+    const int P = c->Mp / (c->xvar ? xrj_rows() : xcd_rows());
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
     const int per_launch = std::max(1, std::min(cus, 256) / P);  // the control block serves 256 workgroups
@@ -581,7 +589,8 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
       x.group_base = gb;
       x.force_fenced = (c->flags & NMFA_FLAG_FORCE_FENCED) ? 1 : 0;
       x.nbuf = c->nbuf;
-      HIP_TRY(launch_anneal_xcd(c->jfmt, a, x, ng, st));
+      if (c->xvar) HIP_TRY(launch_anneal_xrj(a, x, ng, st));
+      else HIP_TRY(launch_anneal_xcd(c->jfmt, a, x, ng, st));
       ++c->launches;
     }
     HIP_TRY(hipEventRecord(c->evm, st));
@@ -754,7 +763,7 @@ extern "C" int nmfa_info(nmfa_ctx* c, int32_t* n, int32_t* precision, int32_t* p
         int rc = sync_ctx(c);
         if (rc) return rc;
       }
-      *path = (c->exchange_mode == 2) ? 3 : 2;
+      *path = ((c->exchange_mode == 2) ? 3 : 2) + (c->xvar ? 2 : 0);
     } else {
       *path = c->path;
     }

@@ -16,6 +16,7 @@ struct nmfa_ctx {
   int path = 0;  // 0 = persistent small-N kernel, 1 = per-iteration kernel, 2 = XCD-group kernel
   int jfmt = 1;              // path 2: J format in LDS (0 BF16, 1 FP8 E4M3, 2 FP4 E2M1)
   int nbuf = 2;              // path 2: spin chunk buffers in LDS (2, 3, 4 or 6)
+  int xvar = 0;              // path 2: 0 = J rows in LDS, 1 = J rows in registers (FP4)
   unsigned* d_ctl = nullptr; // path 2: control block
   bool ctl_pending = false;  // path 2: abort/mode flags not yet read back
   int exchange_mode = 0;     // path 2: 1 = XCD-local, 2 = device-scope fences

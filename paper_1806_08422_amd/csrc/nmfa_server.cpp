@@ -58,7 +58,7 @@ struct Job {
 // Upper bound of the device memory one request needs on any kernel path (J operand copy, exact
 // energy copy, normalisers, schedule, state, spins, energies and the spin operand buffers).
 size_t job_bytes(int n, int R, int t_f, bool j_integral) {
-  const size_t Kp = round_up_sz(n, 128), Mp = round_up_sz(n, 64);
+  const size_t Kp = std::max<size_t>(512, round_up_sz(n, 256)), Mp = round_up_sz(n, 128);  // either XCD layout
   const size_t Rp = round_up_sz(R, 128);
   size_t b = Mp * Kp * 2;                          // J operand (BF16 or smaller)
   b += (size_t)n * n * (j_integral ? 1 : 8);       // J for exact energies

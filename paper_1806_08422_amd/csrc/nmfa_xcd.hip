@@ -29,6 +29,8 @@
 //     is reported to the host as an error.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "nmfa_device.h"
 #include "nmfa_internal.h"
 
@@ -81,13 +83,18 @@ __device__ __forceinline__ bf16x8 fp4x8_to_bf16x8(uint32_t w) {
   return r;
 }
 
-// Wait until at most N of this wave's vector-memory loads are outstanding (N <= 15; LDS and
+// Wait until at most N of this wave's vector-memory operations are outstanding (N <= 63: the
+// counter's low four bits sit in bits 3:0 of the immediate, the high two in bits 15:14; LDS and
 // export counters are not waited on).
 template <int N>
 __device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N <= 15, "vmcnt immediate");
-  __builtin_amdgcn_s_waitcnt(0xF70 | N);
+  static_assert(N >= 0 && N <= 63, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt(0xF70 | (N & 15) | ((N >> 4) << 14));
 }
+
+// Wait until this wave's LDS reads (and scalar loads) are complete; vector-memory counters are
+// left alone.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // Workgroup barrier without the memory fence of __syncthreads (which would also wait for the
 // chunks still in flight); the asm statements keep the compiler from moving LDS accesses across.
@@ -95,6 +102,80 @@ __device__ __forceinline__ void bare_barrier() {
   asm volatile("" ::: "memory");
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
+}
+
+// Where a workgroup sits: its replica group, its row block and the exchange mode.
+struct XcdSlot {
+  unsigned my_group;  // group index within this launch
+  int rb;             // row block
+  bool xcd_mode;      // spins exchanged through the XCD's L2 (no device-scope fences)
+  bool aborted;
+};
+
+// Registration: every workgroup reports its XCD (HW_REG_XCC_ID); when each XCD holds a multiple
+// of P workgroups, groups are formed inside XCDs, else by launch order with device-scope fences.
+// Thread 0 does the work; the result is broadcast through this workgroup's control words.
+__device__ XcdSlot xcd_register(const XcdArgs& x, int tid) {
+  unsigned* ctl = x.ctl;
+  const unsigned P = (unsigned)x.P;
+  if (tid == 0) {
+    const unsigned xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | (15 << 11)) & 0xfu;
+    const unsigned slot = atomicAdd(&ctl[CTL_REG + xcc], 1u);
+    atomicAdd(&ctl[CTL_TOTAL], 1u);
+    unsigned spins = 0;
+    while (ld_dev(&ctl[CTL_TOTAL]) < gridDim.x) {
+      if (++spins > SPIN_LIMIT) {
+        atomicExch(&ctl[CTL_ABORT], 1u);
+        break;
+      }
+    }
+    // XCD-local exchange needs every XCD's workgroup count to be a multiple of P.
+    unsigned base = 0, ok = 1;
+    for (unsigned k = 0; k < 16; ++k) {
+      const unsigned cnt = ld_dev(&ctl[CTL_REG + k]);
+      if (cnt % P) ok = 0;
+      if (k < xcc) base += cnt;
+    }
+    unsigned* info = &ctl[CTL_WG + 4 * blockIdx.x];
+    info[0] = ok ? (base + slot) / P : blockIdx.x / P;
+    info[1] = ok ? slot % P : blockIdx.x % P;
+    info[2] = (ok && !x.force_fenced) ? 1u : 0u;
+    if (blockIdx.x == 0) atomicMax(&ctl[CTL_MODE], (ok && !x.force_fenced) ? 1u : 2u);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+  XcdSlot r;
+  r.my_group = __builtin_amdgcn_readfirstlane(ld_dev(&ctl[CTL_WG + 4 * blockIdx.x]));
+  r.rb = (int)__builtin_amdgcn_readfirstlane(ld_dev(&ctl[CTL_WG + 4 * blockIdx.x + 1]));
+  r.xcd_mode = ld_dev(&ctl[CTL_WG + 4 * blockIdx.x + 2]) != 0;
+  r.aborted = ld_dev(&ctl[CTL_ABORT]) != 0;
+  return r;
+}
+
+// Group barrier after the new spins are stored: arrive on the group's counter, wait for all P
+// workgroups of this epoch (bounded), then make the other workgroups' spins visible. Returns
+// whether the anneal was aborted (a wait timed out somewhere).
+__device__ __forceinline__ bool xcd_group_barrier(const XcdArgs& x, unsigned* bar, unsigned epoch,
+                                                  bool xcd_mode, int tid) {
+  unsigned* ctl = x.ctl;
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores of the new spins are complete
+  __syncthreads();
+  if (tid == 0) {
+    if (!xcd_mode) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = (unsigned)x.P * epoch;
+    unsigned spins = 0;
+    while (ld_dev(bar) < target) {
+      if (++spins > SPIN_LIMIT || ld_dev(&ctl[CTL_ABORT])) {
+        atomicExch(&ctl[CTL_ABORT], 1u);
+        break;
+      }
+    }
+    if (!xcd_mode) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  if (xcd_mode) asm volatile("buffer_inv sc0" ::: "memory");  // drop stale L1 lines
+  return ld_dev(&ctl[CTL_ABORT]) != 0;
 }
 
 // Raw J fragment of one lane for one k-step: 8 values as 16 (BF16), 8 (FP8) or 4 (FP4) bytes.
@@ -130,38 +211,12 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
   unsigned* ctl = x.ctl;
 
   // ---- registration: find the XCD of every workgroup, then agree on the mapping -------------
-  if (tid == 0) {
-    const unsigned xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | (15 << 11)) & 0xfu;
-    const unsigned slot = atomicAdd(&ctl[CTL_REG + xcc], 1u);
-    atomicAdd(&ctl[CTL_TOTAL], 1u);
-    unsigned spins = 0;
-    while (ld_dev(&ctl[CTL_TOTAL]) < gridDim.x) {
-      if (++spins > SPIN_LIMIT) {
-        atomicExch(&ctl[CTL_ABORT], 1u);
-        break;
-      }
-    }
-    // XCD-local exchange needs every XCD's workgroup count to be a multiple of P.
-    unsigned base = 0, ok = 1;
-    for (unsigned k = 0; k < 16; ++k) {
-      const unsigned cnt = ld_dev(&ctl[CTL_REG + k]);
-      if (cnt % (unsigned)P) ok = 0;
-      if (k < xcc) base += cnt;
-    }
-    unsigned* info = &ctl[CTL_WG + 4 * blockIdx.x];
-    info[0] = ok ? (base + slot) / (unsigned)P : blockIdx.x / (unsigned)P;
-    info[1] = ok ? slot % (unsigned)P : blockIdx.x % (unsigned)P;
-    info[2] = (ok && !x.force_fenced) ? 1u : 0u;
-    if (blockIdx.x == 0) atomicMax(&ctl[CTL_MODE], (ok && !x.force_fenced) ? 1u : 2u);
-    __builtin_amdgcn_s_waitcnt(0);
-  }
-  __syncthreads();
-  // broadcast through this workgroup's words of the control block (device-scope loads)
-  const unsigned my_group = ld_dev(&ctl[CTL_WG + 4 * blockIdx.x]);
+  const XcdSlot slot = xcd_register(x, tid);
+  const unsigned my_group = slot.my_group;
   const int group = (int)my_group + x.group_base;
-  const int rb = (int)ld_dev(&ctl[CTL_WG + 4 * blockIdx.x + 1]);
-  const bool xcd_mode = ld_dev(&ctl[CTL_WG + 4 * blockIdx.x + 2]) != 0;
-  bool aborted = ld_dev(&ctl[CTL_ABORT]) != 0;
+  const int rb = slot.rb;
+  const bool xcd_mode = slot.xcd_mode;
+  bool aborted = slot.aborted;
 
   // ---- LDS: J rows (swizzled), ring of S chunk buffers -----------------------------------
   unsigned char* Jl = smem;                           // [64][jrow]
@@ -379,27 +434,7 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
     }
 
     // ---- group barrier ----------------------------------------------------------------------
-    if (t < a.t_end) {
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's stores of the new spins are complete
-      __syncthreads();
-      ++epoch;
-      if (tid == 0) {
-        if (!xcd_mode) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned target = (unsigned)P * (unsigned)epoch;
-        unsigned spins = 0;
-        while (ld_dev(bar) < target) {
-          if (++spins > SPIN_LIMIT || ld_dev(&ctl[CTL_ABORT])) {
-            atomicExch(&ctl[CTL_ABORT], 1u);
-            break;
-          }
-        }
-        if (!xcd_mode) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      }
-      __syncthreads();
-      if (xcd_mode) asm volatile("buffer_inv sc0" ::: "memory");  // drop stale L1 lines
-      aborted = ld_dev(&ctl[CTL_ABORT]) != 0;
-    }
+    if (t < a.t_end) aborted = xcd_group_barrier(x, bar, (unsigned)++epoch, xcd_mode, tid);
   }
 
   // ---- final state and readout ---------------------------------------------------------------
@@ -420,6 +455,243 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
   }
 }
 
+// ---- register-resident J ------------------------------------------------------------------
+// For couplings that FP4 E2M1 holds exactly and N <= 2048: 4 waves per CU, each holding its 32
+// rows of J (FP4, one 32-bit register per 8 couplings: 128 registers at Kp = 2048) for the whole
+// anneal. A workgroup covers 128 rows x 64 replicas, so each widened J fragment feeds four MFMAs
+// and the spin stream per CU is half that of the LDS-resident variant; the whole LDS is a ring of
+// 8 KB spin chunks, deep enough to keep ~112 KB of loads in flight. The k loop is unrolled over
+// all chunks, which makes every register index, buffer index, wait count and load offset a
+// compile-time constant.
+constexpr int XRJ_ROWS = 128;                  // rows of J per workgroup (32 per wave)
+constexpr int XRJ_RG = 64;                     // replicas per group
+constexpr int XRJ_NB = 16;                     // spin chunk buffers in LDS
+constexpr int XRJ_CHB = XRJ_RG * XCD_KC * 2;   // bytes of one chunk: 64 replicas x 64 k, BF16
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+
+// NCH: number of 64-k chunks (Kp = 64 * NCH). RT: 16-row tiles per wave; the 128 rows are
+// split over 8 / RT waves (RT = 2: 4 waves, one per SIMD; RT = 1: 8 waves, two per SIMD).
+template <int NCH, int RT>
+__global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
+    AnnealArgs a, XcdArgs x) {
+  extern __shared__ __align__(16) unsigned char smem[];  // XRJ_NB chunk buffers
+  constexpr int NB = XRJ_NB;
+  constexpr int DPW = RT;  // 1 KB direct-to-LDS loads per wave and chunk (8 KB over 8 / RT waves)
+  static_assert(NB - 3 <= 31 && NCH % 2 == 0, "ring geometry");
+  const int N = a.N, ks = x.ks;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g4 = lane >> 4, c = lane & 15;
+
+  const XcdSlot slot = xcd_register(x, tid);
+  const unsigned my_group = slot.my_group;
+  const int group = (int)my_group + x.group_base;
+  const int rb = slot.rb;
+  const bool xcd_mode = slot.xcd_mode;
+  bool aborted = slot.aborted;
+
+  // J of this wave: jr[ch][q][rt] = the 8 FP4 couplings of row rb*128 + 16*RT*wave + 16*rt + c at
+  // k = 64*ch + 8*(2*g4 + q) .. +7 (lane group g4 takes two adjacent 8-k units per chunk; the
+  // spin fragments below use the same k assignment, and a dot product does not depend on the
+  // order of its terms).
+  uint32_t jr[NCH][2][RT];
+  {
+    const int jrow = 32 * NCH;  // bytes of one FP4 row (Kp / 2)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const unsigned char* p = reinterpret_cast<const unsigned char*>(a.J) +
+                               (size_t)(rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + c) * jrow + 8 * g4;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const uint2 v = *reinterpret_cast<const uint2*>(p + 32 * ch);
+        jr[ch][0][rt] = v.x;
+        jr[ch][1][rt] = v.y;
+      }
+    }
+  }
+
+  const float* inv_g = reinterpret_cast<const float*>(a.inv_norm);
+  const float* h_g = reinterpret_cast<const float*>(a.hterm);
+  float* state = reinterpret_cast<float*>(a.state);
+  float* traj = reinterpret_cast<float*>(a.traj);
+  const float* coef = reinterpret_cast<const float*>(a.coef);
+  float inv[RT][4], hv[RT][4], s[RT][4][4];
+  int row0[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    row0[rt] = rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + 4 * g4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      inv[rt][v] = inv_g[row0[rt] + v];
+      hv[rt][v] = h_g[row0[rt] + v];
+    }
+  }
+  const int rgroup0 = group * XRJ_RG;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int r = rgroup0 + 16 * ct + c;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0[rt] + v;
+        s[rt][ct][v] = (a.load_state && r < a.R && i < N) ? state[(size_t)r * N + i] : 0.0f;
+      }
+  }
+  const float sg = (float)a.sigma;
+  const float neg2ln2_s2 = -2.0f * 0.6931471805599453f * sg * sg;
+  const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha);
+
+  // Spin fragments: replica q = 16*ct + c of the chunk, 16-byte unit u = 2*g4 + kq of its 128-byte
+  // row, stored at unit u ^ (q & 6). Bit 0 of the unit is untouched, so kq = 1 is the next 16
+  // bytes, and eight consecutive replicas fall on distinct banks.
+  int boff[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) boff[ct] = (16 * ct + c) * 128 + ((2 * g4) ^ (c & 6)) * 16;
+  // Direct-to-LDS loads: a chunk is 8 blocks of 1 KB (8 replicas x 128 bytes); wave w loads
+  // blocks DPW*w .. DPW*w + DPW - 1. Lane l fills unit l % 8 of replica 8*blk + l / 8 from the global unit
+  // that the swizzle puts there.
+  unsigned dma_off[DPW];
+#pragma unroll
+  for (int u = 0; u < DPW; ++u) {
+    const int blk = DPW * wave + u;
+    const int q = 8 * blk + (lane >> 3);
+    const int pu = lane & 7;
+    dma_off[u] = (unsigned)(q * ks + (pu ^ (q & 6)) * 8) * 2u;  // bytes within the group's block
+  }
+
+  const __bf16* S0 = reinterpret_cast<const __bf16*>(x.S[0]);
+  const __bf16* S1 = reinterpret_cast<const __bf16*>(x.S[1]);
+  // (the LDS operand of the direct-to-LDS builtin is formed from a pointer variable and plain
+  // integers: with the extern shared array itself, or an element of a local array whose size
+  // depends on a template parameter, in that expression the host compilation pass silently
+  // drops the kernel's launch stub)
+  unsigned char* ring = smem;
+  unsigned* bar = &x.ctl[CTL_BAR + 16 * (int)my_group];
+  int epoch = 0;
+  __syncthreads();
+
+  for (int t = a.t_begin; t <= a.t_end && !aborted; ++t) {
+    const unsigned char* Sg =
+        reinterpret_cast<const unsigned char*>(((t & 1) ? S1 : S0) + (size_t)group * XRJ_RG * ks);
+    __bf16* Snext = const_cast<__bf16*>((t & 1) ? S0 : S1);
+
+    auto issue = [&](int ch, int buf) {
+#pragma unroll
+      for (int u = 0; u < DPW; ++u)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const __bf16*>(Sg + dma_off[u] + ch * 128),
+                                         ring + buf * XRJ_CHB + (DPW * wave + u) * 1024, 16, 0, 0);
+    };
+    bf16x8 fb[2][4];  // [register set][column tile]: the spins of one 32-k step
+    // spin fragments of k step kstep (chunk kstep / 2, half kstep % 2) into register set kstep % 2
+    auto load = [&](int kstep) {
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        fb[kstep & 1][ct] =
+            *reinterpret_cast<const bf16x8*>(smem + ((kstep >> 1) % NB) * XRJ_CHB + boff[ct] + 16 * (kstep & 1));
+    };
+    f32x4 acc[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
+
+    // prologue: the first NB - 1 chunks in flight, wait for chunk 0, read its first k step
+    constexpr int PRO = NB - 1 < NCH ? NB - 1 : NCH;
+#pragma unroll
+    for (int q = 0; q < PRO; ++q) issue(q, q);
+    wait_vm<DPW * (PRO - 1)>();
+    bare_barrier();
+    load(0);
+    // k step ks: the spins of step ks+1 are read into the other register set while the MFMAs
+    // of step ks run. Before the first read of chunk c+1 (in the second step of chunk c) the
+    // workgroup meets at a barrier: chunk c+1 has landed for every wave, and every wave is done
+    // reading chunk c-1, whose buffer then receives chunk c+NB-1.
+    static_for(
+        [&](auto kqc) {
+          constexpr int kstep = decltype(kqc)::value;
+          constexpr int ch = kstep >> 1;
+          if constexpr ((kstep & 1) && ch + 1 < NCH) {
+            constexpr int last_issued = (ch + NB - 2 < NCH - 1) ? ch + NB - 2 : NCH - 1;
+            wait_vm<DPW * (last_issued - (ch + 1))>();
+            __builtin_amdgcn_sched_barrier(0);
+            bare_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (ch + NB - 1 < NCH) issue(ch + NB - 1, (ch + NB - 1) % NB);
+          }
+          // The reads of step kstep (issued a step ago) are complete by now; waiting for them before
+          // issuing those of step kstep+1 keeps the MFMAs below free of any LDS wait.
+          wait_lds();
+          if constexpr (kstep + 1 < 2 * NCH) load(kstep + 1);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+            const bf16x8 af = fp4x8_to_bf16x8(jr[ch][kstep & 1][rt]);
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, fb[kstep & 1][ct], acc[rt][ct], 0, 0, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        },
+        std::make_integer_sequence<int, 2 * NCH>{});
+
+    // ---- fused epilogue --------------------------------------------------------------------
+    const float coef_t = coef[t - 1];
+    const int k_rec = t - a.t_begin;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int r = rgroup0 + 16 * ct + c;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        float z[4];
+        sigma_gauss4_f32(philox4x32_10((uint32_t)(row0[rt] >> 2), (uint32_t)r, (uint32_t)t, 0u, a.key0, a.key1),
+                         neg2ln2_s2, z);
+        __bf16 outv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float xf = fmaf(acc[rt][ct][v], inv[rt][v], hv[rt][v]);
+          const float phi = a.negate_noise ? xf - z[v] : xf + z[v];
+          const float sh = neg_tanh_from_exp2_arg(phi * coef_t);
+          float sv = fmaf(alpha, sh, oma * s[rt][ct][v]);
+          if (row0[rt] + v >= N) sv = 0.0f;
+          s[rt][ct][v] = sv;
+          outv[v] = (__bf16)sv;
+        }
+        *reinterpret_cast<uint2*>(Snext + (size_t)r * ks + row0[rt]) = *reinterpret_cast<const uint2*>(outv);
+        if (traj && k_rec < a.record && r < a.R) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (row0[rt] + v < N) traj[((size_t)k_rec * a.R + r) * N + row0[rt] + v] = s[rt][ct][v];
+        }
+      }
+    }
+
+    if (t < a.t_end) aborted = xcd_group_barrier(x, bar, (unsigned)++epoch, xcd_mode, tid);
+  }
+
+  // ---- final state and readout ---------------------------------------------------------------
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int r = rgroup0 + 16 * ct + c;
+    if (r >= a.R) continue;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0[rt] + v;
+        if (i < N) {
+          state[(size_t)r * N + i] = s[rt][ct][v];
+          if (a.spins) a.spins[(size_t)r * N + i] = (s[rt][ct][v] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
+        }
+      }
+  }
+}
+
 size_t xcd_j_lds_bytes(int jfmt, int Kp) {
   return (size_t)XCD_ROWS * (jfmt == 0 ? (size_t)Kp * 2 : (jfmt == 1 ? (size_t)Kp : (size_t)Kp / 2));
 }
@@ -428,6 +700,27 @@ size_t xcd_chunk_bytes() { return (size_t)XCD_RG * XCD_KC * 2; }
 // Row stride of S. Padding the rows (so that the 128 rows of a chunk do not share their low
 // address bits) was measured to make no difference on MI355X, so the rows are packed.
 int xcd_spin_stride(int Kp) { return Kp; }
+
+int xrj_rows() { return XRJ_ROWS; }
+int xrj_group_replicas() { return XRJ_RG; }
+int xrj_kp(int n) { return n <= 512 ? 512 : ((n + 255) / 256) * 256; }
+bool xrj_fits(int n) { return xrj_kp(n) <= 2048; }
+
+// waves per workgroup of the register-J kernel: 8 (16 rows each, two per SIMD)
+constexpr int XRJ_RT = 1;
+
+static const void* xrj_fn(int Kp) {
+  switch (Kp) {
+    case 512: return (const void*)anneal_xrj<8, XRJ_RT>;
+    case 768: return (const void*)anneal_xrj<12, XRJ_RT>;
+    case 1024: return (const void*)anneal_xrj<16, XRJ_RT>;
+    case 1280: return (const void*)anneal_xrj<20, XRJ_RT>;
+    case 1536: return (const void*)anneal_xrj<24, XRJ_RT>;
+    case 1792: return (const void*)anneal_xrj<28, XRJ_RT>;
+    case 2048: return (const void*)anneal_xrj<32, XRJ_RT>;
+    default: return nullptr;
+  }
+}
 
 int xcd_ctl_words() { return CTL_WORDS; }
 int xcd_rows() { return XCD_ROWS; }
@@ -453,27 +746,39 @@ int xcd_pick_buffers(size_t room) {
   return 0;
 }
 
+// Every workgroup of a launch must be resident at once (they wait for each other). One
+// workgroup fills a CU's LDS, so that holds when the grid does not exceed what the occupancy
+// calculator allows; a launch that cannot become resident (a GPU shared with long-running work)
+// ends in the bounded registration wait with an error rather than hanging. An ordinary launch is
+// used rather than the cooperative-launch API, under which the ROCm profiler cannot trace the
+// process.
+static hipError_t launch_resident(const void* fn, int grid, int block, size_t lds, const AnnealArgs& a,
+                                  const XcdArgs& x, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0, cus = 0, dev = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds);
+  if (e != hipSuccess) return e;
+  if ((long)per_cu * cus < (long)grid) return hipErrorCooperativeLaunchTooLarge;
+  AnnealArgs aa = a;
+  XcdArgs xx = x;
+  void* args[] = {&aa, &xx};
+  return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st);
+}
+
+hipError_t launch_anneal_xrj(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
+  const void* fn = xrj_fn(a.Kp);
+  if (!fn) return hipErrorInvalidValue;
+  return launch_resident(fn, groups * x.P, 64 * 8 / XRJ_RT, (size_t)XRJ_NB * XRJ_CHB, a, x, st);
+}
+
 hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
   const size_t lds = xcd_j_lds_bytes(jfmt, a.Kp) + (size_t)x.nbuf * xcd_chunk_bytes();
   const void* fn = jfmt == 0 ? xcd_fn<0>(x.nbuf) : (jfmt == 1 ? xcd_fn<1>(x.nbuf) : xcd_fn<2>(x.nbuf));
   if (!fn) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  AnnealArgs aa = a;
-  XcdArgs xx = x;
-  void* args[] = {&aa, &xx};
-  // Every workgroup of the launch must be resident at once (they wait for each other). One
-  // workgroup fills a CU's LDS, so that holds when the grid does not exceed the CU count; a
-  // launch that cannot become resident (a GPU shared with long-running work) ends in the bounded
-  // registration wait with an error rather than hanging. An ordinary launch is used rather than
-  // the cooperative-launch API, under which the ROCm profiler cannot trace the process.
-  int per_cu = 0, cus = 0, dev = 0;
-  e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, lds);
-  if (e != hipSuccess) return e;
-  if ((long)per_cu * cus < (long)groups * x.P) return hipErrorCooperativeLaunchTooLarge;
-  return hipLaunchKernel(fn, dim3(groups * x.P), dim3(512), args, lds, st);
+  return launch_resident(fn, groups * x.P, 512, lds, a, x, st);
 }
 
 }  // namespace nmfa

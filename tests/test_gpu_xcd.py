@@ -1,4 +1,5 @@
-"""GPU parity of the persistent XCD-group kernel (large N, BF16 / FP8-J operands).
+"""GPU parity of the persistent XCD-group kernels (large N, BF16 / FP8-J operands): J rows in LDS
+(any exact J format) and J rows in registers (FP4-exact couplings, N <= 2048).
 
 Bars:
 * early trajectory (first 10 iterations) within 5e-3 of the FP64 oracle (BF16 operand rounding
@@ -44,35 +45,73 @@ def _early_traj_check(nmfa, inst, precision, R, t_f, seed, sub, n_rec=10, **kw):
     return path, err, spins, E, Ei
 
 
+def _paths(lds_j):
+    return ("xcd", "xcd_fenced") if lds_j else ("xcd_rj", "xcd_rj_fenced")
+
+
+@pytest.mark.parametrize("lds_j", [True, False])
 @pytest.mark.parametrize("n,R,precision", [(200, 300, "bf16"), (333, 130, "fp8j_bf16s"),
                                            (1000, 129, "bf16"), (70, 40, "fp8j_bf16s")])
-def test_xcd_early_trajectory_and_energies(nmfa, n, R, precision):
+def test_xcd_early_trajectory_and_energies(nmfa, n, R, precision, lds_j):
     inst = instances.sk(n, 3)
     inst.h = np.round(instances.gaussian_fields(n, 1.0, 2))
     sub = [0, R // 2, R - 1]
-    path, err, spins, E, Ei = _early_traj_check(nmfa, inst, precision, R, 400, 17, sub, force_xcd=True)
-    assert path in ("xcd", "xcd_fenced")
+    path, err, spins, E, Ei = _early_traj_check(nmfa, inst, precision, R, 400, 17, sub, force_xcd=True,
+                                                force_lds_j=lds_j)
+    assert path in _paths(lds_j)
     assert err <= 5e-3, err
     assert np.array_equal(Ei, oracle.energies_int(inst.J, inst.h, spins))
 
 
-def test_xcd_local_and_fenced_exchange_agree(nmfa):
-    """P = 4 workgroups per group, 64 groups: 256 workgroups, every XCD holds whole groups."""
+@pytest.mark.parametrize("kind", ["fp8", "bf16"])
+def test_xcd_wider_j_formats(nmfa, kind):
+    """Couplings that FP4 cannot hold: +-5 (FP8-exact) and multiples of 1/64 (BF16 only) run on the
+    LDS-J kernel in FP8 / BF16."""
+    n, R = 400, 200
+    base = instances.sk(n, 11)
+    if kind == "fp8":
+        J = 5.0 * base.J
+    else:
+        rng = np.random.Generator(np.random.PCG64(12))
+        W = np.clip(np.round(rng.normal(0.0, 1.0, (n, n)) * 64.0), -255, 255) / 64.0  # 8 bits: BF16-exact
+        J = np.triu(W, 1)
+        J = J + J.T
+    inst = instances.Instance(J=J, h=np.zeros(n), name=kind)
+    sub = [0, 101, R - 1]
+    with nmfa.Solver(inst.J, inst.h, precision="bf16", record_iters=10) as s:
+        s.anneal(R, 300, 5)
+        traj = s.trajectory()
+        spins = s.spins()
+        E, _ = s.energies()
+        info = s.info()
+    assert info["path"] in ("xcd", "xcd_fenced")
+    assert info["j_format"] == ("fp8_e4m3" if kind == "fp8" else "bf16")
+    _, _, otraj = oracle.anneal(inst.J, inst.h, oracle.schedule(300)[:10], replicas=sub, seed=5, record=10)
+    assert np.max(np.abs(traj[:, sub, :] - otraj)) <= 5e-3
+    assert np.allclose(E, oracle.energies(inst.J, inst.h, spins), rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("lds_j", [True, False])
+def test_xcd_local_and_fenced_exchange_agree(nmfa, lds_j):
+    """64 groups over 256 workgroups (LDS-J: P = 4 x 128 replicas; register-J: P = 2 x 64
+    replicas, 128 groups in two launches): every XCD holds whole groups."""
     inst = instances.gnp(200, 0.3, 5)
     R, t_f = 64 * 128, 300
     out = {}
     for fenced in (False, True):
-        with nmfa.Solver(inst.J, inst.h, precision="bf16", force_xcd=True, force_fenced=fenced) as s:
+        with nmfa.Solver(inst.J, inst.h, precision="bf16", force_xcd=True, force_fenced=fenced,
+                         force_lds_j=lds_j) as s:
             s.anneal(R, t_f, 99)
             out[fenced] = (s.state(), s.info()["path"])
-    assert out[False][1] == "xcd" and out[True][1] == "xcd_fenced"
+    assert out[False][1] == _paths(lds_j)[0] and out[True][1] == _paths(lds_j)[1]
     assert np.array_equal(out[False][0], out[True][0])
 
 
-def test_xcd_replica_prefix_and_resume(nmfa):
+@pytest.mark.parametrize("lds_j", [True, False])
+def test_xcd_replica_prefix_and_resume(nmfa, lds_j):
     inst = instances.sk(300, 8)
     t_f, seed = 250, 4
-    with nmfa.Solver(inst.J, inst.h, precision="bf16", force_xcd=True) as s:
+    with nmfa.Solver(inst.J, inst.h, precision="bf16", force_xcd=True, force_lds_j=lds_j) as s:
         s.anneal(400, t_f, seed)
         full400 = s.state()
         s.anneal(150, t_f, seed)
@@ -90,7 +129,7 @@ def test_full_size_benchmark_configuration(nmfa):
     R, t_f, seed = 1024, 5000, 1000
     sub = [0, 511, 1023]
     path, err, spins, E, Ei = _early_traj_check(nmfa, inst, "fp8j_bf16s", R, t_f, seed, sub, n_rec=5)
-    assert path == "xcd"
+    assert path == "xcd_rj"
     assert err <= 5e-3, err
     rows = np.arange(0, R, 97)
     assert np.array_equal(Ei[rows], oracle.energies_int(inst.J, inst.h, spins[rows]))
@@ -109,7 +148,7 @@ def test_k2000_class_success_vs_fp64(nmfa):
     with nmfa.Solver(inst.J, inst.h, precision="fp8j_bf16s") as s:
         s.anneal(R, t_f, 2025)
         E16 = s.energies()[0]
-        assert s.info()["path"] == "xcd"
+        assert s.info()["path"] == "xcd_rj"
     target = float(np.percentile(E_ref, 10))
     p64 = stats.success_probability(E64, target)
     p16 = stats.success_probability(E16, target)
