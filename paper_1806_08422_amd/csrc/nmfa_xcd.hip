@@ -460,28 +460,29 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
 // rows of J (FP4, one 32-bit register per 8 couplings: 128 registers at Kp = 2048) for the whole
 // anneal. A workgroup covers 128 rows x 64 replicas, so each widened J fragment feeds four MFMAs
 // and the spin stream per CU is half that of the LDS-resident variant; the whole LDS is a ring of
-// 8 KB spin chunks, deep enough to keep ~112 KB of loads in flight. The k loop is unrolled over
+// 16 KB spin chunks, deep enough to keep ~96 KB of loads in flight. The k loop is unrolled over
 // all chunks, which makes every register index, buffer index, wait count and load offset a
 // compile-time constant.
 constexpr int XRJ_ROWS = 128;                  // rows of J per workgroup (32 per wave)
 constexpr int XRJ_RG = 64;                     // replicas per group
-constexpr int XRJ_NB = 16;                     // spin chunk buffers in LDS
-constexpr int XRJ_CHB = XRJ_RG * XCD_KC * 2;   // bytes of one chunk: 64 replicas x 64 k, BF16
+constexpr int XRJ_KC = 128;                    // k per spin chunk (four 32-k MFMA steps)
+constexpr int XRJ_NB = 8;                      // spin chunk buffers in LDS
+constexpr int XRJ_CHB = XRJ_RG * XRJ_KC * 2;   // bytes of one chunk: 64 replicas x 128 k, BF16
 
 template <class F, int... I>
 __device__ __forceinline__ void static_for(F&& f, std::integer_sequence<int, I...>) {
   (f(std::integral_constant<int, I>{}), ...);
 }
 
-// NCH: number of 64-k chunks (Kp = 64 * NCH). RT: 16-row tiles per wave; the 128 rows are
+// NCH: number of 128-k chunks (Kp = 128 * NCH). RT: 16-row tiles per wave; the 128 rows are
 // split over 8 / RT waves (RT = 2: 4 waves, one per SIMD; RT = 1: 8 waves, two per SIMD).
 template <int NCH, int RT>
 __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
     AnnealArgs a, XcdArgs x) {
   extern __shared__ __align__(16) unsigned char smem[];  // XRJ_NB chunk buffers
   constexpr int NB = XRJ_NB;
-  constexpr int DPW = RT;  // 1 KB direct-to-LDS loads per wave and chunk (8 KB over 8 / RT waves)
-  static_assert(NB - 3 <= 31 && NCH % 2 == 0, "ring geometry");
+  constexpr int DPW = 2 * RT;  // 1 KB direct-to-LDS loads per wave and chunk (16 KB over 8 / RT waves)
+  static_assert(DPW * (NB - 3) <= 63, "ring geometry");
   const int N = a.N, ks = x.ks;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g4 = lane >> 4, c = lane & 15;
@@ -494,21 +495,23 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
   bool aborted = slot.aborted;
 
   // J of this wave: jr[ch][q][rt] = the 8 FP4 couplings of row rb*128 + 16*RT*wave + 16*rt + c at
-  // k = 64*ch + 8*(2*g4 + q) .. +7 (lane group g4 takes two adjacent 8-k units per chunk; the
+  // k = 128*ch + 8*(4*g4 + q) .. +7 (lane group g4 takes four adjacent 8-k units per chunk; the
   // spin fragments below use the same k assignment, and a dot product does not depend on the
   // order of its terms).
-  uint32_t jr[NCH][2][RT];
+  uint32_t jr[NCH][4][RT];
   {
-    const int jrow = 32 * NCH;  // bytes of one FP4 row (Kp / 2)
+    const int jrow = 64 * NCH;  // bytes of one FP4 row (Kp / 2)
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       const unsigned char* p = reinterpret_cast<const unsigned char*>(a.J) +
-                               (size_t)(rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + c) * jrow + 8 * g4;
+                               (size_t)(rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + c) * jrow + 16 * g4;
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) {
-        const uint2 v = *reinterpret_cast<const uint2*>(p + 32 * ch);
+        const uint4 v = *reinterpret_cast<const uint4*>(p + 64 * ch);
         jr[ch][0][rt] = v.x;
         jr[ch][1][rt] = v.y;
+        jr[ch][2][rt] = v.z;
+        jr[ch][3][rt] = v.w;
       }
     }
   }
@@ -545,22 +548,24 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
   const float neg2ln2_s2 = -2.0f * 0.6931471805599453f * sg * sg;
   const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha);
 
-  // Spin fragments: replica q = 16*ct + c of the chunk, 16-byte unit u = 2*g4 + kq of its 128-byte
-  // row, stored at unit u ^ (q & 6). Bit 0 of the unit is untouched, so kq = 1 is the next 16
-  // bytes, and eight consecutive replicas fall on distinct banks.
+  // Spin fragments: replica q = 16*ct + c of the chunk, 16-byte unit u = 4*g4 + kq of its 256-byte
+  // row, stored at unit u ^ (q & 15). A ds_read_b128 serves 16 lanes per cycle; their 16 replicas
+  // then hit 16 distinct units, i.e. all 64 banks once, so the reads are conflict free. q & 15
+  // does not depend on ct, so the column tiles are 4 KB apart and one base offset per k step
+  // serves all four.
   int boff[4];
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) boff[ct] = (16 * ct + c) * 128 + ((2 * g4) ^ (c & 6)) * 16;
-  // Direct-to-LDS loads: a chunk is 8 blocks of 1 KB (8 replicas x 128 bytes); wave w loads
-  // blocks DPW*w .. DPW*w + DPW - 1. Lane l fills unit l % 8 of replica 8*blk + l / 8 from the global unit
-  // that the swizzle puts there.
+  for (int kq = 0; kq < 4; ++kq) boff[kq] = c * 256 + ((4 * g4 + kq) ^ c) * 16;
+  // Direct-to-LDS loads: a chunk is 16 blocks of 1 KB (4 replicas x 256 bytes); wave w loads
+  // blocks DPW*w .. DPW*w + DPW - 1. Lane l fills unit l % 16 of replica 4*blk + l / 16 from the
+  // global unit that the swizzle puts there.
   unsigned dma_off[DPW];
 #pragma unroll
   for (int u = 0; u < DPW; ++u) {
     const int blk = DPW * wave + u;
-    const int q = 8 * blk + (lane >> 3);
-    const int pu = lane & 7;
-    dma_off[u] = (unsigned)(q * ks + (pu ^ (q & 6)) * 8) * 2u;  // bytes within the group's block
+    const int q = 4 * blk + (lane >> 4);
+    const int pu = lane & 15;
+    dma_off[u] = (unsigned)(q * ks + (pu ^ (q & 15)) * 8) * 2u;  // bytes within the group's block
   }
 
   const __bf16* S0 = reinterpret_cast<const __bf16*>(x.S[0]);
@@ -582,16 +587,16 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
     auto issue = [&](int ch, int buf) {
 #pragma unroll
       for (int u = 0; u < DPW; ++u)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const __bf16*>(Sg + dma_off[u] + ch * 128),
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const __bf16*>(Sg + dma_off[u] + ch * 2 * XRJ_KC),
                                          ring + buf * XRJ_CHB + (DPW * wave + u) * 1024, 16, 0, 0);
     };
     bf16x8 fb[2][4];  // [register set][column tile]: the spins of one 32-k step
-    // spin fragments of k step kstep (chunk kstep / 2, half kstep % 2) into register set kstep % 2
+    // spin fragments of k step kstep (chunk kstep / 4, quarter kstep % 4) into register set kstep % 2
     auto load = [&](int kstep) {
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct)
         fb[kstep & 1][ct] =
-            *reinterpret_cast<const bf16x8*>(smem + ((kstep >> 1) % NB) * XRJ_CHB + boff[ct] + 16 * (kstep & 1));
+            *reinterpret_cast<const bf16x8*>(smem + ((kstep >> 2) % NB) * XRJ_CHB + boff[kstep & 3] + 4096 * ct);
     };
     f32x4 acc[RT][4];
 #pragma unroll
@@ -609,14 +614,14 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
     bare_barrier();
     load(0);
     // k step ks: the spins of step ks+1 are read into the other register set while the MFMAs
-    // of step ks run. Before the first read of chunk c+1 (in the second step of chunk c) the
+    // of step ks run. Before the first read of chunk c+1 (in the last step of chunk c) the
     // workgroup meets at a barrier: chunk c+1 has landed for every wave, and every wave is done
     // reading chunk c-1, whose buffer then receives chunk c+NB-1.
     static_for(
         [&](auto kqc) {
           constexpr int kstep = decltype(kqc)::value;
-          constexpr int ch = kstep >> 1;
-          if constexpr ((kstep & 1) && ch + 1 < NCH) {
+          constexpr int ch = kstep >> 2;
+          if constexpr ((kstep & 3) == 3 && ch + 1 < NCH) {
             constexpr int last_issued = (ch + NB - 2 < NCH - 1) ? ch + NB - 2 : NCH - 1;
             wait_vm<DPW * (last_issued - (ch + 1))>();
             __builtin_amdgcn_sched_barrier(0);
@@ -627,18 +632,18 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
           // The reads of step kstep (issued a step ago) are complete by now; waiting for them before
           // issuing those of step kstep+1 keeps the MFMAs below free of any LDS wait.
           wait_lds();
-          if constexpr (kstep + 1 < 2 * NCH) load(kstep + 1);
+          if constexpr (kstep + 1 < 4 * NCH) load(kstep + 1);
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt) {
-            const bf16x8 af = fp4x8_to_bf16x8(jr[ch][kstep & 1][rt]);
+            const bf16x8 af = fp4x8_to_bf16x8(jr[ch][kstep & 3][rt]);
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct)
               acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, fb[kstep & 1][ct], acc[rt][ct], 0, 0, 0);
           }
           __builtin_amdgcn_sched_barrier(0);
         },
-        std::make_integer_sequence<int, 2 * NCH>{});
+        std::make_integer_sequence<int, 4 * NCH>{});
 
     // ---- fused epilogue --------------------------------------------------------------------
     const float coef_t = coef[t - 1];
@@ -706,18 +711,18 @@ int xrj_group_replicas() { return XRJ_RG; }
 int xrj_kp(int n) { return n <= 512 ? 512 : ((n + 255) / 256) * 256; }
 bool xrj_fits(int n) { return xrj_kp(n) <= 2048; }
 
-// waves per workgroup of the register-J kernel: 8 (16 rows each, two per SIMD)
-constexpr int XRJ_RT = 1;
+// 16-row tiles per wave of the register-J kernel: 2 (4 waves of 32 rows, one per SIMD)
+constexpr int XRJ_RT = 2;
 
 static const void* xrj_fn(int Kp) {
   switch (Kp) {
-    case 512: return (const void*)anneal_xrj<8, XRJ_RT>;
-    case 768: return (const void*)anneal_xrj<12, XRJ_RT>;
-    case 1024: return (const void*)anneal_xrj<16, XRJ_RT>;
-    case 1280: return (const void*)anneal_xrj<20, XRJ_RT>;
-    case 1536: return (const void*)anneal_xrj<24, XRJ_RT>;
-    case 1792: return (const void*)anneal_xrj<28, XRJ_RT>;
-    case 2048: return (const void*)anneal_xrj<32, XRJ_RT>;
+    case 512: return (const void*)anneal_xrj<4, XRJ_RT>;
+    case 768: return (const void*)anneal_xrj<6, XRJ_RT>;
+    case 1024: return (const void*)anneal_xrj<8, XRJ_RT>;
+    case 1280: return (const void*)anneal_xrj<10, XRJ_RT>;
+    case 1536: return (const void*)anneal_xrj<12, XRJ_RT>;
+    case 1792: return (const void*)anneal_xrj<14, XRJ_RT>;
+    case 2048: return (const void*)anneal_xrj<16, XRJ_RT>;
     default: return nullptr;
   }
 }
