@@ -152,17 +152,26 @@ __device__ XcdSlot xcd_register(const XcdArgs& x, int tid) {
   return r;
 }
 
-// Group barrier after the new spins are stored: arrive on the group's counter, wait for all P
-// workgroups of this epoch (bounded), then make the other workgroups' spins visible. Returns
-// whether the anneal was aborted (a wait timed out somewhere).
-__device__ __forceinline__ bool xcd_group_barrier(const XcdArgs& x, unsigned* bar, unsigned epoch,
-                                                  bool xcd_mode, int tid) {
-  unsigned* ctl = x.ctl;
+// Group barrier after the new spins are stored, in two halves so that work which does not
+// depend on the other workgroups can run in between. Arrive: this workgroup's stores are
+// complete (and released to the device when the group spans XCDs); one thread adds to the
+// group's counter.
+__device__ __forceinline__ void xcd_group_arrive(unsigned* bar, bool xcd_mode, int tid) {
   __builtin_amdgcn_s_waitcnt(0);  // this wave's stores of the new spins are complete
   __syncthreads();
   if (tid == 0) {
     if (!xcd_mode) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Wait: one thread polls until all P workgroups have arrived for this epoch (bounded), then the
+// other workgroups' spins are made visible. Returns whether the anneal was aborted (a wait timed
+// out somewhere).
+__device__ __forceinline__ bool xcd_group_wait(const XcdArgs& x, unsigned* bar, unsigned epoch, bool xcd_mode,
+                                               int tid) {
+  unsigned* ctl = x.ctl;
+  if (tid == 0) {
     const unsigned target = (unsigned)x.P * epoch;
     unsigned spins = 0;
     while (ld_dev(bar) < target) {
@@ -176,6 +185,12 @@ __device__ __forceinline__ bool xcd_group_barrier(const XcdArgs& x, unsigned* ba
   __syncthreads();
   if (xcd_mode) asm volatile("buffer_inv sc0" ::: "memory");  // drop stale L1 lines
   return ld_dev(&ctl[CTL_ABORT]) != 0;
+}
+
+__device__ __forceinline__ bool xcd_group_barrier(const XcdArgs& x, unsigned* bar, unsigned epoch,
+                                                  bool xcd_mode, int tid) {
+  xcd_group_arrive(bar, xcd_mode, tid);
+  return xcd_group_wait(x, bar, epoch, xcd_mode, tid);
 }
 
 // Raw J fragment of one lane for one k-step: 8 values as 16 (BF16), 8 (FP8) or 4 (FP4) bytes.
@@ -547,6 +562,19 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
   const float sg = (float)a.sigma;
   const float neg2ln2_s2 = -2.0f * 0.6931471805599453f * sg * sg;
   const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha);
+  // sigma * z for this lane's 4 x (4 RT) spins of iteration tt (noise does not depend on the state,
+  // so it is drawn ahead: while the group barrier of the previous iteration completes)
+  float zn[RT][4][4];
+  auto draw_noise = [&](int tt) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        sigma_gauss4_f32(philox4x32_10((uint32_t)(row0[rt] >> 2), (uint32_t)(rgroup0 + 16 * ct + c), (uint32_t)tt, 0u,
+                                       a.key0, a.key1),
+                         neg2ln2_s2, zn[rt][ct]);
+  };
+  draw_noise(a.t_begin);
 
   // Spin fragments: replica q = 16*ct + c of the chunk, 16-byte unit u = 4*g4 + kq of its 256-byte
   // row, stored at unit u ^ (q & 15). A ds_read_b128 serves 16 lanes per cycle; their 16 replicas
@@ -653,14 +681,11 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
       const int r = rgroup0 + 16 * ct + c;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        float z[4];
-        sigma_gauss4_f32(philox4x32_10((uint32_t)(row0[rt] >> 2), (uint32_t)r, (uint32_t)t, 0u, a.key0, a.key1),
-                         neg2ln2_s2, z);
         __bf16 outv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float xf = fmaf(acc[rt][ct][v], inv[rt][v], hv[rt][v]);
-          const float phi = a.negate_noise ? xf - z[v] : xf + z[v];
+          const float phi = a.negate_noise ? xf - zn[rt][ct][v] : xf + zn[rt][ct][v];
           const float sh = neg_tanh_from_exp2_arg(phi * coef_t);
           float sv = fmaf(alpha, sh, oma * s[rt][ct][v]);
           if (row0[rt] + v >= N) sv = 0.0f;
@@ -676,7 +701,20 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
       }
     }
 
-    if (t < a.t_end) aborted = xcd_group_barrier(x, bar, (unsigned)++epoch, xcd_mode, tid);
+    if (t < a.t_end) {
+      xcd_group_arrive(bar, xcd_mode, tid);
+      draw_noise(t + 1);
+      // Pin the draw between arrival and wait: the values are only used in the next iteration, so
+      // the compiler would otherwise sink the draw past the wait onto the critical path. An empty
+      // volatile statement that reads each value cannot move across the wait's synchronisation.
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(zn[rt][ct][v]));
+      aborted = xcd_group_wait(x, bar, (unsigned)++epoch, xcd_mode, tid);
+    }
   }
 
   // ---- final state and readout ---------------------------------------------------------------
