@@ -122,6 +122,10 @@ static void free_run_buffers(nmfa_ctx* c) {
   (void)hipFree(c->d_spins);
   (void)hipFree(c->d_E);
   (void)hipFree(c->d_Eint);
+  (void)hipFree(c->d_Sp);
+  (void)hipFree(c->d_E2);
+  c->d_Sp = nullptr;
+  c->d_E2 = nullptr;
   (void)hipFree(c->d_S[0]);
   (void)hipFree(c->d_S[1]);
   c->d_state = nullptr;
@@ -401,10 +405,13 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     CREATE_TRY(hipMemcpy(c->d_hterm, fh.data(), Mp * 4, hipMemcpyHostToDevice));
   }
   if (use_J8) {
-    std::vector<int8_t> j8(nn);
-    for (size_t k = 0; k < nn; ++k) j8[k] = (int8_t)Jf[k];
-    CREATE_TRY(hipMalloc(&c->d_J8, nn));
-    CREATE_TRY(hipMemcpy(c->d_J8, j8.data(), nn, hipMemcpyHostToDevice));
+    c->Np8 = (int)round_up(n, 64);
+    const size_t np = (size_t)c->Np8 * c->Np8;
+    std::vector<int8_t> j8(np, 0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) j8[(size_t)i * c->Np8 + j] = (int8_t)Jf[(size_t)i * n + j];
+    CREATE_TRY(hipMalloc(&c->d_J8, np));
+    CREATE_TRY(hipMemcpy(c->d_J8, j8.data(), np, hipMemcpyHostToDevice));
   } else {
     CREATE_TRY(hipMalloc(&c->d_J64, nn * 8));
     CREATE_TRY(hipMemcpy(c->d_J64, Jf.data(), nn * 8, hipMemcpyHostToDevice));
@@ -435,6 +442,10 @@ static int ensure_run_buffers(nmfa_ctx* c, int R) {
     HIP_TRY(hipMalloc(&c->d_spins, cnt));
     HIP_TRY(hipMalloc(&c->d_E, (size_t)R * 8));
     HIP_TRY(hipMalloc(&c->d_Eint, (size_t)R * 8));
+    if (c->d_J8) {
+      HIP_TRY(hipMalloc(&c->d_Sp, round_up(R, 64) * (size_t)c->Np8));
+      HIP_TRY(hipMalloc(&c->d_E2, (size_t)R * 8));
+    }
     c->cap_R = R;
     c->state_valid = false;
   }
@@ -537,8 +548,11 @@ int ctx_prepare_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_
 
 // Energies of the readout and the completion bookkeeping of one anneal call.
 int ctx_finish_run(nmfa_ctx* c, hipStream_t st) {
-  HIP_TRY(launch_energy(c->d_J8, c->d_J64, c->d_h, c->h_integral ? 1 : 0, c->d_spins, c->n, c->R, c->d_Eint,
-                        c->d_E, st));
+  if (c->d_J8)
+    HIP_TRY(launch_energy_i8(c->d_J8, c->Np8, c->d_h, c->h_integral ? 1 : 0, c->d_spins, c->n, c->R, c->d_Sp,
+                             c->d_E2, c->d_Eint, c->d_E, st));
+  else
+    HIP_TRY(launch_energy(nullptr, c->d_J64, c->d_h, 0, c->d_spins, c->n, c->R, c->d_Eint, c->d_E, st));
   HIP_TRY(hipEventRecord(c->ev1, st));
   c->timed = true;
   c->state_valid = true;
@@ -680,12 +694,21 @@ extern "C" int nmfa_energies_of(nmfa_ctx* c, int32_t R, const int8_t* spins, dou
   int8_t* d_s = nullptr;
   double* d_E = nullptr;
   long long* d_Ei = nullptr;
+  int8_t* d_Sp = nullptr;
+  unsigned long long* d_E2 = nullptr;
   const size_t cnt = (size_t)R * c->n;
   hipError_t e = hipMalloc(&d_s, cnt);
   if (e == hipSuccess) e = hipMalloc(&d_E, (size_t)R * 8);
   if (e == hipSuccess) e = hipMalloc(&d_Ei, (size_t)R * 8);
+  if (e == hipSuccess && c->d_J8) e = hipMalloc(&d_Sp, round_up(R, 64) * (size_t)c->Np8);
+  if (e == hipSuccess && c->d_J8) e = hipMalloc(&d_E2, (size_t)R * 8);
   if (e == hipSuccess) e = hipMemcpy(d_s, spins, cnt, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_energy(c->d_J8, c->d_J64, c->d_h, c->h_integral ? 1 : 0, d_s, c->n, R, d_Ei, d_E, 0);
+  if (e == hipSuccess) {
+    if (c->d_J8)
+      e = launch_energy_i8(c->d_J8, c->Np8, c->d_h, c->h_integral ? 1 : 0, d_s, c->n, R, d_Sp, d_E2, d_Ei, d_E, 0);
+    else
+      e = launch_energy(nullptr, c->d_J64, c->d_h, 0, d_s, c->n, R, d_Ei, d_E, 0);
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(E, d_E, (size_t)R * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess && E_int) {
@@ -695,6 +718,8 @@ extern "C" int nmfa_energies_of(nmfa_ctx* c, int32_t R, const int8_t* spins, dou
   (void)hipFree(d_s);
   (void)hipFree(d_E);
   (void)hipFree(d_Ei);
+  (void)hipFree(d_Sp);
+  (void)hipFree(d_E2);
   if (e != hipSuccess) return fail(NMFA_EDEVICE, "nmfa_energies_of: %s", hipGetErrorString(e));
   return NMFA_OK;
 }

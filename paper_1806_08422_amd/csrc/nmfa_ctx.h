@@ -36,7 +36,8 @@ struct nmfa_ctx {
   void* d_J = nullptr;       // operand layout of the selected path
   void* d_inv = nullptr;     // [Mp] acc_t
   void* d_hterm = nullptr;   // [Mp] acc_t
-  int8_t* d_J8 = nullptr;    // [n][n] for exact energies (integral |J| <= 127)
+  int8_t* d_J8 = nullptr;    // [Np8][Np8] zero-padded, for exact energies (integral |J| <= 127)
+  int Np8 = 0;               // roundup(n, 64)
   double* d_J64 = nullptr;   // [n][n] otherwise
   double* d_h = nullptr;     // [n] or null
 
@@ -51,6 +52,8 @@ struct nmfa_ctx {
   int8_t* d_spins = nullptr; // [R][n]
   double* d_E = nullptr;     // [R]
   long long* d_Eint = nullptr;
+  int8_t* d_Sp = nullptr;    // energy scratch: padded signs [roundup(R, 64)][Np8]
+  unsigned long long* d_E2 = nullptr;  // energy scratch [R]
   void* d_S[2] = {nullptr, nullptr};  // paths 1 and 2: [Rp][Ks] op_t
   int cap_Rp = 0;
   void* d_traj = nullptr;

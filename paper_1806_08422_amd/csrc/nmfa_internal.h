@@ -65,6 +65,11 @@ hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R,
 hipError_t launch_readout(int prec, const void* state, int8_t* spins, size_t count, hipStream_t st);
 hipError_t launch_energy(const int8_t* J8, const double* J64, const double* h, int h_integral,
                          const int8_t* spins, int N, int R, long long* E_int, double* E, hipStream_t st);
+// Exact energies for integral |J| <= 127 on the int8 matrix cores. J8p: [Np][Np] zero-padded
+// (Np a multiple of 64); Sp: scratch of roundup(R, 64) * Np bytes; E2: scratch of R int64.
+hipError_t launch_energy_i8(const int8_t* J8p, int Np, const double* h, int h_integral, const int8_t* spins,
+                            int N, int R, int8_t* Sp, unsigned long long* E2, long long* E_int, double* E,
+                            hipStream_t st);
 hipError_t launch_noise_words(uint32_t k0, uint32_t k1, uint32_t t, uint32_t r0, int nrep, int nq,
                               uint32_t* out, hipStream_t st);
 hipError_t launch_noise_values(uint32_t k0, uint32_t k1, uint32_t t, uint32_t r0, int nrep, int nq,

@@ -445,6 +445,85 @@ __global__ __launch_bounds__(256) void energy_kernel(const int8_t* __restrict__ 
 }
 
 // ------------------------------------------------------------------------------------------
+// Exact energies on the matrix cores, for integral couplings |J_ij| <= 127 (int8): the pair term
+// sum_i s_i y_i with y = J s is an int8 x int8 -> int32 matrix product (v_mfma_i32_16x16x64_i8),
+// exact in any summation order. Operands are zero-padded copies: J8p [Np][Np] and the signs
+// Sp [Rp][Np] (Np a multiple of 64, Rp of 64), so the kernel needs no bounds checks. Each wave
+// computes y for 16 rows x 64 replicas, forms s_i y_i for its rows and adds the per-replica sums
+// to E2 with 64-bit integer atomics (exact, order-free). A finishing pass adds the field term
+// with the arithmetic of energy_kernel, so both paths give identical energies.
+// ------------------------------------------------------------------------------------------
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void pad_spins_kernel(const int8_t* __restrict__ s, int N, int R, int8_t* __restrict__ Sp, int Np,
+                                 int Rp) {
+  const size_t total = (size_t)Rp * Np;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / Np), i = (int)(idx - (size_t)r * Np);
+    Sp[idx] = (r < R && i < N) ? s[(size_t)r * N + i] : (int8_t)0;
+  }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// grid (Np / 64, Rp / 64), block 256: wave w owns rows 64*bx + 16w .. +15, replicas 64*by .. +63
+__global__ __launch_bounds__(256) void energy_pairs_i8(const int8_t* __restrict__ J8p, const int8_t* __restrict__ Sp,
+                                                       int Np, int R, unsigned long long* __restrict__ E2) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 15, g4 = lane >> 4;
+  const int row0 = blockIdx.x * 64 + wave * 16;
+  const int rep0 = blockIdx.y * 64;
+  // lane group g4 supplies k = 16 g4 .. 16 g4 + 15 of every 64-k step, for A (J) and B (signs) alike
+  const int8_t* a_ptr = J8p + (size_t)(row0 + c) * Np + 16 * g4;
+  i32x4 acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = i32x4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < Np; k0 += 64) {
+    const i32x4 av = *reinterpret_cast<const i32x4*>(a_ptr + k0);
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const i32x4 bv = *reinterpret_cast<const i32x4*>(Sp + (size_t)(rep0 + 16 * ct + c) * Np + 16 * g4 + k0);
+      acc[ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc[ct], 0, 0, 0);
+    }
+  }
+  // lane (c, g4) holds y of rows row0 + 4 g4 + v for replica rep0 + 16 ct + c
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int r = rep0 + 16 * ct + c;
+    const int sv = *reinterpret_cast<const int*>(Sp + (size_t)r * Np + row0 + 4 * g4);  // 4 signs
+    int part = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part += (int)(int8_t)(sv >> (8 * v)) * acc[ct][v];
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (g4 == 0 && r < R) atomicAdd(&E2[r], (unsigned long long)(long long)part);
+  }
+}
+
+// E_int = (sum_i s_i y_i) / 2 + integral field term; E as energy_kernel computes it
+__global__ void energy_finish_kernel(const unsigned long long* __restrict__ E2, const double* __restrict__ h,
+                                     int h_integral, const int8_t* __restrict__ spins, int N, int R,
+                                     long long* __restrict__ E_int, double* __restrict__ E) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int8_t* s = spins + (size_t)r * N;
+  long long fld = 0;
+  double field_real = 0.0;
+  if (h && h_integral) {
+    for (int i = 0; i < N; ++i) fld += (long long)h[i] * (long long)s[i];
+  } else if (h) {
+    for (int i = 0; i < N; ++i) field_real += h[i] * (double)s[i];
+  }
+  const long long e2 = (long long)E2[r] + 2 * fld;
+  if (E_int) E_int[r] = e2 / 2;
+  E[r] = (h && !h_integral) ? (double)(e2 / 2) + field_real : (double)(e2 / 2);
+}
+
+// ------------------------------------------------------------------------------------------
 // Noise words / values for a range of spins (library utility and test hook for the stream).
 // words: out[(k*n + i)] for replica r0 + k ... see nmfa.h.
 // ------------------------------------------------------------------------------------------
@@ -546,6 +625,20 @@ hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, 
       break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_i8(const int8_t* J8p, int Np, const double* h, int h_integral, const int8_t* spins,
+                            int N, int R, int8_t* Sp, unsigned long long* E2, long long* E_int, double* E,
+                            hipStream_t st) {
+  const int Rp = (R + 63) / 64 * 64;
+  const size_t total = (size_t)Rp * Np;
+  const int pb = (int)std::min<size_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(pad_spins_kernel, dim3(pb), dim3(256), 0, st, spins, N, R, Sp, Np, Rp);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((R + 255) / 256), dim3(256), 0, st, E2, R);
+  hipLaunchKernelGGL(energy_pairs_i8, dim3(Np / 64, Rp / 64), dim3(256), 0, st, J8p, (const int8_t*)Sp, Np, R, E2);
+  hipLaunchKernelGGL(energy_finish_kernel, dim3((R + 127) / 128), dim3(128), 0, st, (const unsigned long long*)E2,
+                     h, h_integral, spins, N, R, E_int, E);
   return hipGetLastError();
 }
 
