@@ -48,7 +48,7 @@ def measured_traffic(path: str):
     when the kernel source has changed since the counters were taken (or another path ran)."""
     import hashlib
 
-    prof = os.path.join(ROOT, "profiles", "anneal_xcd_g2000_r1024_tf5000_hbm_bytes.md")
+    prof = os.path.join(ROOT, "profiles", "anneal_xrj_g2000_r1024_tf5000_hbm_bytes.md")
     src = os.path.join(ROOT, "paper_1806_08422_amd", "csrc", "nmfa_xcd.hip")
     try:
         fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
