@@ -74,6 +74,7 @@ typedef enum nmfa_precision {
 #define NMFA_FLAG_FORCE_FENCED 0x10u  /* XCD-group kernel: exchange with device-scope fences */
 #define NMFA_FLAG_FORCE_LDS_J 0x20u   /* XCD-group kernel: keep J in LDS even where the
                                          register-resident variant applies (test hook) */
+#define NMFA_FLAG_FORCE_SPARSE 0x40u  /* use the sparse (ELL) kernel: at most 64 couplings per row */
 
 /* ---- parameters ------------------------------------------------------------------------------
  * Fill with nmfa_params_default() and override fields. struct_size must be sizeof(nmfa_params)
@@ -155,7 +156,8 @@ int nmfa_trajectory(nmfa_ctx *c, double *out);
  * J rows in LDS whose groups exchanged spins through one XCD's L2; 3 = the same kernel with
  * device-scope fences, used when a group's workgroups were not all placed on one XCD; 4 and 5 =
  * the XCD-group kernel with J rows held in registers (FP4-exact couplings, n <= 2048), exchange
- * as for 2 and 3). Paths 2/3 and 4/5 are only told apart after an anneal has completed (the call
+ * as for 2 and 3; 6 = the sparse kernel, J as nonzeros per row (chosen for n > 256 when every
+ * row has at most min(64, n/8) couplings, or with NMFA_FLAG_FORCE_SPARSE)). Paths 2/3 and 4/5 are only told apart after an anneal has completed (the call
  * synchronises). Errors: EINVAL, EDEVICE. */
 int nmfa_info(nmfa_ctx *c, int32_t *n, int32_t *precision, int32_t *path);
 
@@ -168,6 +170,7 @@ int nmfa_info(nmfa_ctx *c, int32_t *n, int32_t *precision, int32_t *path);
 #define NMFA_JFMT_FP8 1
 #define NMFA_JFMT_FP4 2
 #define NMFA_JFMT_NATIVE 3
+#define NMFA_JFMT_ELL 4 /* sparse kernel: nonzeros per row with column indices, FP32 (FP64 for FP64) */
 int nmfa_j_format(nmfa_ctx *c, int32_t *fmt);
 
 /* Device time of the last anneal in milliseconds, from HIP events recorded on the anneal's own

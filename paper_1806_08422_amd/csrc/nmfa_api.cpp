@@ -162,6 +162,8 @@ extern "C" void nmfa_destroy(nmfa_ctx* c) {
   (void)hipFree(c->d_hterm);
   (void)hipFree(c->d_J8);
   (void)hipFree(c->d_J64);
+  (void)hipFree(c->d_ell_col);
+  (void)hipFree(c->d_ell_val);
   (void)hipFree(c->d_h);
   (void)hipFree(c->d_traj);
   (void)hipFree(c->d_coef);
@@ -295,8 +297,27 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   const bool x_ok = bf && Mp_x / xcd_rows() <= 32 && x_nbuf >= 2;
   // register-resident-J variant of the XCD-group kernel: FP4-exact couplings, n <= 2048
   const bool x_rj = x_ok && x_jfmt == 2 && xrj_fits(n) && !(p->flags & NMFA_FLAG_FORCE_LDS_J);
+  // sparse (ELL) kernel: maximum degree D <= 64 and the workgroup's state fits in LDS
+  int deg_max = 0;
+  for (int i = 0; i < n; ++i) {
+    int d = 0;
+    for (int j = 0; j < n; ++j) d += (Jf[(size_t)i * n + j] != 0.0) ? 1 : 0;
+    deg_max = std::max(deg_max, d);
+  }
+  const int sp_prec = (c->prec == NMFA_FP64) ? 0 : 1;  // kernel arithmetic: FP64 or FP32
+  int sp_rb = 0;
+  for (int rb : {8, 4, 2, 1})
+    if (sparse_lds_bytes(sp_prec, n, rb) <= (size_t)64 * 1024) { sp_rb = rb; break; }
+  if (!sp_rb && sparse_lds_bytes(sp_prec, n, 1) <= (size_t)device_max_lds()) sp_rb = 1;
+  const bool sp_ok = deg_max <= 64 && sp_rb > 0;
+  const bool sp_auto = sp_ok && n > 256 && 8 * std::max(deg_max, 1) <= n;
   if (p->flags & NMFA_FLAG_FORCE_STEP) {
     c->path = 1;
+  } else if (p->flags & NMFA_FLAG_FORCE_SPARSE) {
+    if (!sp_ok)
+      return fail(NMFA_EINVAL, "nmfa_create: the sparse kernel needs at most 64 couplings per row and a state "
+                               "that fits in LDS (n = %d, maximum degree %d)", n, deg_max);
+    c->path = 3;
   } else if ((p->flags & NMFA_FLAG_FORCE_XCD) && x_ok) {
     c->path = 2;
   } else if ((p->flags & NMFA_FLAG_FORCE_XCD)) {
@@ -304,6 +325,8 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
                              "couplings that fit its LDS");
   } else if (small_fits) {
     c->path = 0;
+  } else if (sp_auto) {
+    c->path = 3;
   } else if (x_ok) {
     c->path = 2;
   } else {
@@ -313,6 +336,12 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->Mp = Mp_s;
     c->Kp = Kp_s;
     c->lds_stride = stride_s;
+  } else if (c->path == 3) {
+    c->Mp = (int)round_up(n, 4);
+    c->Kp = c->Mp;
+    c->lds_stride = 0;
+    c->ell_D = std::max(deg_max, 1);
+    c->sp_RB = sp_rb;
   } else if (c->path == 2 && x_rj) {
     c->xvar = 1;
     c->Mp = (int)round_up(n, xrj_rows());
@@ -349,11 +378,12 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   const bool j8_small = (c->prec == NMFA_FP8J_BF16S && c->path == 0);
   const int jfmt2 = (c->path == 2) ? c->jfmt : -1;
   size_t jbytes;
-  if (j8_small || jfmt2 == 1) jbytes = (size_t)Mp * Kp;
+  if (c->path == 3) jbytes = 0;  // the sparse kernel reads its ELL copy instead
+  else if (j8_small || jfmt2 == 1) jbytes = (size_t)Mp * Kp;
   else if (jfmt2 == 2) jbytes = (size_t)Mp * Kp / 2;
   else jbytes = (size_t)Mp * Kp * (jfmt2 == 0 ? 2 : es);
   std::vector<unsigned char> jbuf(jbytes, 0);
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n && jbytes; ++i) {
     for (int j = 0; j < n; ++j) {
       double v = Jf[(size_t)i * n + j];
       if (c->prec == NMFA_FP8J_BF16S) v = fp8e4m3_value(fp8e4m3_bits(v));
@@ -387,8 +417,45 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
                                #expr, hipGetErrorString(_e)));                                      \
   } while (0)
 
-  CREATE_TRY(hipMalloc(&c->d_J, jbytes));
-  CREATE_TRY(hipMemcpy(c->d_J, jbuf.data(), jbytes, hipMemcpyHostToDevice));
+  if (jbytes) {
+    CREATE_TRY(hipMalloc(&c->d_J, jbytes));
+    CREATE_TRY(hipMemcpy(c->d_J, jbuf.data(), jbytes, hipMemcpyHostToDevice));
+  }
+  if (c->path == 3) {
+    // ELL rows: the nonzeros of row i in ascending column order, padded with (i, 0); values
+    // rounded as the precision prescribes (FP8 / BF16 / FP32), held in FP32 (FP64 for FP64)
+    const int D = c->ell_D;
+    std::vector<int> col((size_t)n * D);
+    std::vector<double> vd((size_t)n * D, 0.0);
+    for (int i = 0; i < n; ++i) {
+      int d = 0;
+      for (int j = 0; j < n; ++j) {
+        double v = Jf[(size_t)i * n + j];
+        if (v == 0.0) continue;
+        if (c->prec == NMFA_FP8J_BF16S) v = fp8e4m3_value(fp8e4m3_bits(v));
+        else if (c->prec == NMFA_BF16) {
+          const uint32_t b = (uint32_t)bf16_bits(v) << 16;
+          float f;
+          std::memcpy(&f, &b, 4);
+          v = f;
+        } else if (c->prec == NMFA_FP32) v = (float)v;
+        col[(size_t)i * D + d] = j;
+        vd[(size_t)i * D + d] = v;
+        ++d;
+      }
+      for (; d < D; ++d) col[(size_t)i * D + d] = i;
+    }
+    CREATE_TRY(hipMalloc(&c->d_ell_col, col.size() * sizeof(int)));
+    CREATE_TRY(hipMemcpy(c->d_ell_col, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (c->prec == NMFA_FP64) {
+      CREATE_TRY(hipMalloc(&c->d_ell_val, vd.size() * 8));
+      CREATE_TRY(hipMemcpy(c->d_ell_val, vd.data(), vd.size() * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> vf(vd.begin(), vd.end());
+      CREATE_TRY(hipMalloc(&c->d_ell_val, vf.size() * 4));
+      CREATE_TRY(hipMemcpy(c->d_ell_val, vf.data(), vf.size() * 4, hipMemcpyHostToDevice));
+    }
+  }
   const size_t as = c->acc_size();
   CREATE_TRY(hipMalloc(&c->d_inv, Mp * as));
   CREATE_TRY(hipMalloc(&c->d_hterm, Mp * as));
@@ -574,6 +641,10 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
   HIP_TRY(hipEventRecord(c->ev0, st));
   if (c->path == 0) {
     HIP_TRY(launch_anneal_small(c->prec, a, st));
+    c->launches = 1;
+    HIP_TRY(hipEventRecord(c->evm, st));
+  } else if (c->path == 3) {
+    HIP_TRY(launch_anneal_sparse(c->prec == NMFA_FP64 ? 0 : 1, a, c->d_ell_col, c->d_ell_val, c->ell_D, c->sp_RB, st));
     c->launches = 1;
     HIP_TRY(hipEventRecord(c->evm, st));
   } else if (c->path == 2) {
@@ -790,7 +861,7 @@ extern "C" int nmfa_info(nmfa_ctx* c, int32_t* n, int32_t* precision, int32_t* p
       }
       *path = ((c->exchange_mode == 2) ? 3 : 2) + (c->xvar ? 2 : 0);
     } else {
-      *path = c->path;
+      *path = (c->path == 3) ? 6 : c->path;
     }
   }
   return NMFA_OK;
@@ -799,6 +870,7 @@ extern "C" int nmfa_info(nmfa_ctx* c, int32_t* n, int32_t* precision, int32_t* p
 extern "C" int nmfa_j_format(nmfa_ctx* c, int32_t* fmt) {
   if (!c || !fmt) return fail(NMFA_EINVAL, "nmfa_j_format: NULL argument");
   if (c->path == 2) *fmt = c->jfmt;
+  else if (c->path == 3) *fmt = NMFA_JFMT_ELL;
   else if (c->prec == NMFA_FP64 || c->prec == NMFA_FP32) *fmt = NMFA_JFMT_NATIVE;
   else if (c->prec == NMFA_FP8J_BF16S && c->path == 0) *fmt = NMFA_JFMT_FP8;
   else *fmt = NMFA_JFMT_BF16;

@@ -39,6 +39,10 @@ struct nmfa_ctx {
   int8_t* d_J8 = nullptr;    // [Np8][Np8] zero-padded, for exact energies (integral |J| <= 127)
   int Np8 = 0;               // roundup(n, 64)
   double* d_J64 = nullptr;   // [n][n] otherwise
+  int* d_ell_col = nullptr;  // path 3: [n][ell_D] column indices (ascending, padded with i)
+  void* d_ell_val = nullptr; // path 3: [n][ell_D] couplings (FP64 for the FP64 precision, else FP32)
+  int ell_D = 0;             // path 3: entries per row (maximum degree)
+  int sp_RB = 0;             // path 3: replicas per workgroup
   double* d_h = nullptr;     // [n] or null
 
   // per-run buffers

@@ -65,6 +65,11 @@ hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R,
 hipError_t launch_readout(int prec, const void* state, int8_t* spins, size_t count, hipStream_t st);
 hipError_t launch_energy(const int8_t* J8, const double* J64, const double* h, int h_integral,
                          const int8_t* spins, int N, int R, long long* E_int, double* E, hipStream_t st);
+// Sparse couplings in ELL form (D entries per row, ascending columns, zero-weight padding; values
+// in the accumulation type of prec: FP64 for PREC_FP64, else FP32); RB replicas per workgroup.
+size_t sparse_lds_bytes(int prec, int N, int RB);
+hipError_t launch_anneal_sparse(int prec, const AnnealArgs& a, const int* ell_col, const void* ell_val, int D,
+                                int RB, hipStream_t st);
 // Exact energies for integral |J| <= 127 on the int8 matrix cores. J8p: [Np][Np] zero-padded
 // (Np a multiple of 64); Sp: scratch of roundup(R, 64) * Np bytes; E2: scratch of R int64.
 hipError_t launch_energy_i8(const int8_t* J8p, int Np, const double* h, int h_integral, const int8_t* spins,

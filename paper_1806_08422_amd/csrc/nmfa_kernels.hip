@@ -445,6 +445,86 @@ __global__ __launch_bounds__(256) void energy_kernel(const int8_t* __restrict__ 
 }
 
 // ------------------------------------------------------------------------------------------
+// anneal_sparse<P>: sparse couplings (degree-d graphs). J is stored row by row in ELL form, the
+// nonzeros of row i in ascending column order padded to D entries with zero weights, so the
+// field sum_j J_ij s_j is the dense sum with its exact zero terms left out (bit-identical up to
+// the FMA contraction of each term). One workgroup owns RB replicas and all N spins for the whole
+// anneal: the state of its replicas sits in LDS, double-buffered by iteration parity (layout
+// [Nq][RB], replica fastest, so the threads of one spin gather consecutive words), and a
+// workgroup barrier separates iterations. Thread tasks are (quad q of 4 consecutive spins,
+// replica): one Philox call draws exactly the quad's noise, and the update is the shared
+// Epilogue. FP64 precision runs in FP64; the other precisions run in FP32.
+// ------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void anneal_sparse(AnnealArgs a, const int* __restrict__ ell_col,
+                                                     const void* __restrict__ ell_val, int D, int RB) {
+  using acc_t = typename Traits<P>::acc_t;
+  extern __shared__ __align__(16) unsigned char smem_sp[];
+  const int N = a.N, Nq = (N + 3) / 4;
+  acc_t* buf0 = reinterpret_cast<acc_t*>(smem_sp);
+  acc_t* buf1 = buf0 + (size_t)4 * Nq * RB;
+  const acc_t* val = reinterpret_cast<const acc_t*>(ell_val);
+  const acc_t* inv_g = reinterpret_cast<const acc_t*>(a.inv_norm);
+  const acc_t* h_g = reinterpret_cast<const acc_t*>(a.hterm);
+  const acc_t* coef = reinterpret_cast<const acc_t*>(a.coef);
+  acc_t* state = reinterpret_cast<acc_t*>(a.state);
+  acc_t* traj = reinterpret_cast<acc_t*>(a.traj);
+  const int r0 = blockIdx.x * RB;
+  const int slots = 4 * Nq * RB;
+  for (int idx = threadIdx.x; idx < slots; idx += blockDim.x) {
+    const int i = idx / RB, rr = idx - i * RB, r = r0 + rr;
+    buf0[idx] = (a.load_state && r < a.R && i < N) ? state[(size_t)r * N + i] : (acc_t)0;
+  }
+  __syncthreads();
+  int cur = 0;
+  const int tasks = Nq * RB;
+  for (int t = a.t_begin; t <= a.t_end; ++t) {
+    const acc_t coef_t = coef[t - 1];
+    const acc_t* sc = cur ? buf1 : buf0;
+    acc_t* sn = cur ? buf0 : buf1;
+    const int k_rec = t - a.t_begin;
+    for (int task = threadIdx.x; task < tasks; task += blockDim.x) {
+      const int q = task / RB, rr = task - q * RB, r = r0 + rr;
+      acc_t acc[4], inv[4], hv[4], sv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * q + v;
+        acc_t f = (acc_t)0;
+        if (i < N) {
+          const int* cl = ell_col + (size_t)i * D;
+          const acc_t* vl = val + (size_t)i * D;
+          for (int d = 0; d < D; ++d) f += vl[d] * sc[cl[d] * RB + rr];
+          inv[v] = inv_g[i];
+          hv[v] = h_g[i];
+        } else {
+          inv[v] = (acc_t)0;
+          hv[v] = (acc_t)0;
+        }
+        acc[v] = f;
+        sv[v] = sc[i * RB + rr];
+      }
+      Epilogue<P>::apply(acc, inv, hv, sv, a, coef_t, (uint32_t)q, (uint32_t)r, (uint32_t)t);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * q + v;
+        sn[i * RB + rr] = (i < N) ? sv[v] : (acc_t)0;
+        if (traj && k_rec < a.record && r < a.R && i < N) traj[((size_t)k_rec * a.R + r) * N + i] = sv[v];
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const acc_t* sf = cur ? buf1 : buf0;
+  for (int idx = threadIdx.x; idx < slots; idx += blockDim.x) {
+    const int i = idx / RB, rr = idx - i * RB, r = r0 + rr;
+    if (r < a.R && i < N) {
+      state[(size_t)r * N + i] = sf[idx];
+      if (a.spins) a.spins[(size_t)r * N + i] = (sf[idx] >= (acc_t)0) ? (int8_t)1 : (int8_t)-1;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Exact energies on the matrix cores, for integral couplings |J_ij| <= 127 (int8): the pair term
 // sum_i s_i y_i with y = J s is an int8 x int8 -> int32 matrix product (v_mfma_i32_16x16x64_i8),
 // exact in any summation order. Operands are zero-padded copies: J8p [Np][Np] and the signs
@@ -625,6 +705,24 @@ hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, 
       break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+size_t sparse_lds_bytes(int prec, int N, int RB) {
+  return (size_t)2 * 4 * ((N + 3) / 4) * RB * (prec == PREC_FP64 ? 8 : 4);
+}
+
+hipError_t launch_anneal_sparse(int prec, const AnnealArgs& a, const int* ell_col, const void* ell_val, int D,
+                                int RB, hipStream_t st) {
+  const int grid = (a.R + RB - 1) / RB;
+  const size_t lds = sparse_lds_bytes(prec, a.N, RB);
+  const void* fn = prec == PREC_FP64 ? (const void*)anneal_sparse<PREC_FP64> : (const void*)anneal_sparse<PREC_FP32>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL((anneal_sparse<PREC_FP64>), dim3(grid), dim3(256), lds, st, a, ell_col, ell_val, D, RB);
+  else
+    hipLaunchKernelGGL((anneal_sparse<PREC_FP32>), dim3(grid), dim3(256), lds, st, a, ell_col, ell_val, D, RB);
   return hipGetLastError();
 }
 
