@@ -11,8 +11,9 @@ timing starts.
 
 Prints ONE JSON line. Metric: spin-updates/s = N * R * t_f / (seconds per anneal). Alongside:
 the FP64 GPU path on the same workload (speed-up), TTS99 at N=2000 and N=100, the N=100 dense
-MAX-CUT timing workload of the paper (time per sample), the roofline of the dominant kernel and
-the CPU oracle timed on a bounded sample.
+MAX-CUT timing workload of the paper (time per sample), a random 3-regular MAX-CUT instance at
+N=2000 on the sparse kernel against the dense kernel, the roofline of the dominant kernel and the
+CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -33,6 +34,9 @@ if ROOT not in sys.path:
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# Vector ALU issue peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
+# (half the 157.3 TFLOP/s FP32 vector figure, which counts packed FMAs as 4 flops per lane)
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def tts99(t_sample_s: float, p: float) -> float:
@@ -59,6 +63,25 @@ def measured_traffic(path: str):
     if fields.get("kernel_source_sha256", "").strip() != sha or fields.get("kernel_path", "").strip() != path:
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def measured_valu_instructions(path: str):
+    """Wave-level VALU instructions per launch of the sparse kernel on the 3-regular workload, from
+    the committed counter summary, or None when the kernel source changed since (or another path ran)."""
+    import hashlib
+
+    prof = os.path.join(ROOT, "profiles", "anneal_sparse_rq_d3_n2000_r1024_tf5000_valu.md")
+    src = os.path.join(ROOT, "paper_1806_08422_amd", "csrc", "nmfa_kernels.hip")
+    keys = ("valu_instructions_per_launch", "kernel_source_sha256", "kernel_path")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
+                      if ": " in line and line.split(": ", 1)[0] in keys)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != sha or fields.get("kernel_path", "").strip() != path:
+        return None
+    return float(fields["valu_instructions_per_launch"])
 
 
 def timed_anneals(solver, R, t_f, seeds, stream):
@@ -179,6 +202,9 @@ def serving_leg(nmfa, instances_mod, n_burst: int, n_stream: int, budget_bytes: 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("g2000", "d3_2000"), default="g2000",
+                    help="g2000: dense G(2000, 0.5) MAX-CUT (default); d3_2000: random 3-regular "
+                         "MAX-CUT at N = 2000 on the sparse kernel")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -206,13 +232,12 @@ def main() -> int:
     stream = torch.cuda.current_stream().cuda_stream
 
     N, R, T_F = 2000, 1024, 5000
-    inst = instances.gnp(N, 0.5, 1)
+    dense = args.workload == "g2000"
+    inst = instances.gnp(N, 0.5, 1) if dense else instances.random_regular(N, 3, 1)
     spin_updates = N * R * T_F
-    flops_per_iter = 2.0 * N * N * R  # algorithmic: 2N flops per spin update
+    flops_per_iter = 2.0 * N * N * R  # algorithmic: 2N flops per spin update (dense J)
 
     solver = nmfa.Solver(inst.J, inst.h, precision="fp8j_bf16s")
-    info = solver.info()
-    path, jfmt = info["path"], info["j_format"]
     for w in range(args.warmup):
         solver.anneal(R, T_F, 500 + w, stream)
     torch.cuda.synchronize()
@@ -227,6 +252,8 @@ def main() -> int:
     wall_s = time.perf_counter() - t0
     # per-step device timings of the last step (events on the anneal's stream)
     tm = solver.last_timing()
+    info = solver.info()  # after an anneal: the kernel variants that ran are told apart
+    path, jfmt = info["path"], info["j_format"]
     ms_per_step = wall_s * 1e3 / args.steps
     E16, _ = solver.energies()
     energies.append(E16)
@@ -236,6 +263,28 @@ def main() -> int:
     flops_per_launch = flops_per_iter * (T_F / tm["launches"])
     achieved_tflops = flops_per_launch / (kernel_ms * 1e-3) / 1e12
     value = spin_updates / (ms_per_step * 1e-3)
+    if dense:
+        workload = ("dense random-graph MAX-CUT G(2000,0.5), J in {0,1}, h=0, R=1024, t_f=5000, "
+                    "J rounded to FP8-E4M3 (exact here) / spins BF16 / FP32 accumulate")
+        roofline = {
+            "bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_BF16_TFLOPS, "traffic": measured_traffic(path),
+            "kernel_avg_ms": kernel_ms, "launches_per_step": tm["launches"],
+            "flops_per_launch": flops_per_launch,
+        }
+    else:
+        workload = ("random 3-regular MAX-CUT, N=2000, J in {0,1}, h=0, R=1024, t_f=5000, sparse "
+                    "(ELL) kernel, FP32 arithmetic")
+        # VALU-bound: the per-replica epilogue (Philox, Box-Muller, tanh) dominates; achieved =
+        # counted VALU lane-operations (wave instructions x 64) per second of the kernel
+        vi = measured_valu_instructions(path)
+        ach = None if vi is None else vi * 64 / (kernel_ms * 1e-3) / 1e12
+        roofline = {
+            "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+            "frac": None if ach is None else ach / PEAK_VALU_TOPS, "traffic": None,
+            "kernel_avg_ms": kernel_ms, "launches_per_step": tm["launches"],
+            "valu_instructions_per_launch": vi,
+        }
 
     result = {
         "metric": "spin-updates/s",
@@ -248,26 +297,15 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "bf16" if dense else "f32",
         "data": "synthetic",
         "config": {
-            "workload": "dense random-graph MAX-CUT G(2000,0.5), J in {0,1}, h=0, R=1024, t_f=5000, "
-                        "J rounded to FP8-E4M3 (exact here) / spins BF16 / FP32 accumulate",
+            "workload": workload,
             "n": N, "replicas": R, "t_f": T_F, "precision": "fp8j_bf16s", "kernel_path": path,
             "j_storage": jfmt,
             "parallelism": "single GPU",
         },
-        "roofline": {
-            "bound": "mfma",
-            "achieved": achieved_tflops,
-            "peak": PEAK_BF16_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / PEAK_BF16_TFLOPS,
-            "traffic": measured_traffic(path),
-            "kernel_avg_ms": kernel_ms,
-            "launches_per_step": tm["launches"],
-            "flops_per_launch": flops_per_launch,
-        },
+        "roofline": roofline,
     }
 
     if args.calib_copy_mib > 0:
@@ -280,7 +318,7 @@ def main() -> int:
         del src, dst
 
     extra = {}
-    if not args.no_extra:
+    if not args.no_extra and dense:
         # FP64 GPU path on the same workload: the 5x comparator
         with nmfa.Solver(inst.J, inst.h, precision="fp64") as s64:
             walls, tms = timed_anneals(s64, R, T_F, [77], stream)
@@ -332,6 +370,20 @@ def main() -> int:
             "speedup_vs_fp64": msd / msb,
             "E_target": target, "p_bf16": pb, "p_fp64": pd,
             "tts99_s_bf16": tts99(msb * 1e-3 / 16384, pb), "tts99_s_fp64": tts99(msd * 1e-3 / 16384, pd),
+        }
+        # random 3-regular MAX-CUT at N = 2000 (a degree-3 graph, as in the paper's sparse
+        # instances): the sparse kernel the library picks against the dense matrix-core kernel
+        d3 = instances.random_regular(2000, 3, 1)
+        with nmfa.Solver(d3.J, d3.h, precision="fp8j_bf16s") as ss:
+            ws, _ = timed_anneals(ss, R, T_F, [41, 42], stream)
+            sp_path = ss.info()["path"]
+        with nmfa.Solver(d3.J, d3.h, precision="fp8j_bf16s", force_xcd=True) as sx:
+            wx, _ = timed_anneals(sx, R, T_F, [43], stream)
+        msd3 = float(min(ws))
+        extra["degree3_maxcut_n2000"] = {
+            "R": R, "t_f": T_F, "kernel_path": sp_path, "ms_per_anneal": msd3,
+            "spin_updates_per_s": N * R * T_F / (msd3 * 1e-3),
+            "dense_kernel_ms_per_anneal": wx[0], "speedup_vs_dense": wx[0] / msd3,
         }
         mc = instances.gnp(100, 0.5, 1)
         with nmfa.Solver(mc.J, mc.h, precision="bf16") as sm:

@@ -75,6 +75,8 @@ typedef enum nmfa_precision {
 #define NMFA_FLAG_FORCE_LDS_J 0x20u   /* XCD-group kernel: keep J in LDS even where the
                                          register-resident variant applies (test hook) */
 #define NMFA_FLAG_FORCE_SPARSE 0x40u  /* use the sparse (ELL) kernel: at most 64 couplings per row */
+#define NMFA_FLAG_SPARSE_GENERIC 0x80u /* sparse kernel: read the couplings from global memory every
+                                         iteration even where the register variant applies (test hook) */
 
 /* ---- parameters ------------------------------------------------------------------------------
  * Fill with nmfa_params_default() and override fields. struct_size must be sizeof(nmfa_params)
@@ -157,7 +159,11 @@ int nmfa_trajectory(nmfa_ctx *c, double *out);
  * device-scope fences, used when a group's workgroups were not all placed on one XCD; 4 and 5 =
  * the XCD-group kernel with J rows held in registers (FP4-exact couplings, n <= 2048), exchange
  * as for 2 and 3; 6 = the sparse kernel, J as nonzeros per row (chosen for n > 256 when every
- * row has at most min(64, n/8) couplings, or with NMFA_FLAG_FORCE_SPARSE)). Paths 2/3 and 4/5 are only told apart after an anneal has completed (the call
+ * row has at most min(64, n/8) couplings and either the register variant below applies or no
+ * XCD-group kernel does, or with NMFA_FLAG_FORCE_SPARSE); 7 = the sparse kernel with each
+ * thread's rows of J held in registers (at most 16 couplings per row, n <= 4096, fewer
+ * couplings per row above n = 2048).
+ * Paths 2/3, 4/5 and 6/7 are only told apart after an anneal has completed (the call
  * synchronises). Errors: EINVAL, EDEVICE. */
 int nmfa_info(nmfa_ctx *c, int32_t *n, int32_t *precision, int32_t *path);
 

@@ -310,7 +310,11 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     if (sparse_lds_bytes(sp_prec, n, rb) <= (size_t)64 * 1024) { sp_rb = rb; break; }
   if (!sp_rb && sparse_lds_bytes(sp_prec, n, 1) <= (size_t)device_max_lds()) sp_rb = 1;
   const bool sp_ok = deg_max <= 64 && sp_rb > 0;
-  const bool sp_auto = sp_ok && n > 256 && 8 * std::max(deg_max, 1) <= n;
+  // chosen by itself where the register-ELL kernel serves it (2-4x faster than the dense kernels
+  // at n = 2000, degree 3-16), or where no persistent dense kernel applies; the generic ELL
+  // kernel, which reads J from global memory every iteration, is slower than the XCD kernel
+  const bool sp_rq = sp_ok && sparse_rq_applies(sp_prec, n, std::max(deg_max, 1));
+  const bool sp_auto = sp_ok && n > 256 && 8 * std::max(deg_max, 1) <= n && (sp_rq || !x_ok);
   if (p->flags & NMFA_FLAG_FORCE_STEP) {
     c->path = 1;
   } else if (p->flags & NMFA_FLAG_FORCE_SPARSE) {
@@ -644,7 +648,8 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     c->launches = 1;
     HIP_TRY(hipEventRecord(c->evm, st));
   } else if (c->path == 3) {
-    HIP_TRY(launch_anneal_sparse(c->prec == NMFA_FP64 ? 0 : 1, a, c->d_ell_col, c->d_ell_val, c->ell_D, c->sp_RB, st));
+    HIP_TRY(launch_anneal_sparse(c->prec == NMFA_FP64 ? 0 : 1, a, c->d_ell_col, c->d_ell_val, c->ell_D, c->sp_RB,
+                                 (c->flags & NMFA_FLAG_SPARSE_GENERIC) ? 0 : 1, &c->sp_rq, st));
     c->launches = 1;
     HIP_TRY(hipEventRecord(c->evm, st));
   } else if (c->path == 2) {
@@ -861,7 +866,7 @@ extern "C" int nmfa_info(nmfa_ctx* c, int32_t* n, int32_t* precision, int32_t* p
       }
       *path = ((c->exchange_mode == 2) ? 3 : 2) + (c->xvar ? 2 : 0);
     } else {
-      *path = (c->path == 3) ? 6 : c->path;
+      *path = (c->path == 3) ? 6 + c->sp_rq : c->path;
     }
   }
   return NMFA_OK;

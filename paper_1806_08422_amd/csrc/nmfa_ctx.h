@@ -42,7 +42,8 @@ struct nmfa_ctx {
   int* d_ell_col = nullptr;  // path 3: [n][ell_D] column indices (ascending, padded with i)
   void* d_ell_val = nullptr; // path 3: [n][ell_D] couplings (FP64 for the FP64 precision, else FP32)
   int ell_D = 0;             // path 3: entries per row (maximum degree)
-  int sp_RB = 0;             // path 3: replicas per workgroup
+  int sp_RB = 0;             // path 3: replicas per workgroup (generic ELL kernel)
+  int sp_rq = 0;             // path 3: the last anneal ran the register-ELL kernel
   double* d_h = nullptr;     // [n] or null
 
   // per-run buffers

@@ -67,9 +67,12 @@ hipError_t launch_energy(const int8_t* J8, const double* J64, const double* h, i
                          const int8_t* spins, int N, int R, long long* E_int, double* E, hipStream_t st);
 // Sparse couplings in ELL form (D entries per row, ascending columns, zero-weight padding; values
 // in the accumulation type of prec: FP64 for PREC_FP64, else FP32); RB replicas per workgroup.
+// allow_rq: use the register-ELL kernel where it applies; *used_rq (if not null) tells whether it ran.
+// sparse_rq_applies: the register-ELL kernel serves (prec, N, D) for any replica count.
 size_t sparse_lds_bytes(int prec, int N, int RB);
+int sparse_rq_applies(int prec, int N, int D);
 hipError_t launch_anneal_sparse(int prec, const AnnealArgs& a, const int* ell_col, const void* ell_val, int D,
-                                int RB, hipStream_t st);
+                                int RB, int allow_rq, int* used_rq, hipStream_t st);
 // Exact energies for integral |J| <= 127 on the int8 matrix cores. J8p: [Np][Np] zero-padded
 // (Np a multiple of 64); Sp: scratch of roundup(R, 64) * Np bytes; E2: scratch of R int64.
 hipError_t launch_energy_i8(const int8_t* J8p, int Np, const double* h, int h_integral, const int8_t* spins,

@@ -40,6 +40,9 @@ struct Epilogue<PREC_FP64> {
   __device__ static __forceinline__ void apply(const double acc[4], const double inv[4],
                                                const double h[4], double s[4], const AnnealArgs& a,
                                                double coef_t, uint32_t q, uint32_t r, uint32_t t) {
+    // every operation rounded on its own (no contraction into FMAs), so that all kernels that
+    // share this epilogue round alike, whatever the surrounding code lets the compiler fuse
+#pragma clang fp contract(off)
     double z[4];
     gauss4_f64(philox4x32_10(q, r, t, 0u, a.key0, a.key1), z);
     const double sg = a.negate_noise ? -a.sigma : a.sigma;
@@ -455,8 +458,12 @@ __global__ __launch_bounds__(256) void energy_kernel(const int8_t* __restrict__ 
 // replica): one Philox call draws exactly the quad's noise, and the update is the shared
 // Epilogue. FP64 precision runs in FP64; the other precisions run in FP32.
 // ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float fma_acc(float x, float y, float z) { return __builtin_fmaf(x, y, z); }
+__device__ __forceinline__ double fma_acc(double x, double y, double z) { return __builtin_fma(x, y, z); }
+
 template <int P>
-__global__ __launch_bounds__(256) void anneal_sparse(AnnealArgs a, const int* __restrict__ ell_col,
+__global__ __launch_bounds__(P == PREC_FP64 ? 512 : 1024) void anneal_sparse(AnnealArgs a,
+                                                                             const int* __restrict__ ell_col,
                                                      const void* __restrict__ ell_val, int D, int RB) {
   using acc_t = typename Traits<P>::acc_t;
   extern __shared__ __align__(16) unsigned char smem_sp[];
@@ -493,7 +500,7 @@ __global__ __launch_bounds__(256) void anneal_sparse(AnnealArgs a, const int* __
         if (i < N) {
           const int* cl = ell_col + (size_t)i * D;
           const acc_t* vl = val + (size_t)i * D;
-          for (int d = 0; d < D; ++d) f += vl[d] * sc[cl[d] * RB + rr];
+          for (int d = 0; d < D; ++d) f = fma_acc(vl[d], sc[cl[d] * RB + rr], f);
           inv[v] = inv_g[i];
           hv[v] = h_g[i];
         } else {
@@ -520,6 +527,142 @@ __global__ __launch_bounds__(256) void anneal_sparse(AnnealArgs a, const int* __
     if (r < a.R && i < N) {
       state[(size_t)r * N + i] = sf[idx];
       if (a.spins) a.spins[(size_t)r * N + i] = (sf[idx] >= (acc_t)0) ? (int8_t)1 : (int8_t)-1;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// anneal_sparse_rq<P, RB, DM, QP>: the sparse kernel with the couplings in registers. A thread
+// owns the quads q = tid + k * blockDim.x (k < QP) for all RB replicas of its workgroup and for
+// the whole anneal: its ELL rows (DM entries each, those beyond D zero-weight) are read from
+// global memory once, the quads' own state stays in registers, and one neighbour read is one
+// vector LDS load of that spin's RB replica values (layout [4 Nq][RB], replica fastest, as in
+// anneal_sparse). Each replica's arithmetic (terms in ELL order, one FMA each, noise counters,
+// epilogue) is that of anneal_sparse; a zero-weight term adds a signed zero to a sum that starts
+// at +0 and so changes nothing. Both kernels therefore give bit-identical trajectories, whatever
+// RB and whichever kernel the launcher picks.
+// ------------------------------------------------------------------------------------------
+template <typename T, int RB>
+struct alignas(sizeof(T) * RB) RepVec {
+  T v[RB];
+};
+
+template <int P, int RB, int DM, int QP>
+__global__ __launch_bounds__(512) void anneal_sparse_rq(AnnealArgs a, const int* __restrict__ ell_col,
+                                                       const void* __restrict__ ell_val, int D) {
+  using acc_t = typename Traits<P>::acc_t;
+  using V = RepVec<acc_t, RB>;
+  extern __shared__ __align__(16) unsigned char smem_sp[];
+  const int N = a.N, Nq = (N + 3) / 4;
+  const int buf_bytes = 4 * Nq * (int)sizeof(V);
+  const acc_t* val = reinterpret_cast<const acc_t*>(ell_val);
+  const acc_t* inv_g = reinterpret_cast<const acc_t*>(a.inv_norm);
+  const acc_t* h_g = reinterpret_cast<const acc_t*>(a.hterm);
+  const acc_t* coef = reinterpret_cast<const acc_t*>(a.coef);
+  acc_t* state = reinterpret_cast<acc_t*>(a.state);
+  acc_t* traj = reinterpret_cast<acc_t*>(a.traj);
+  const int r0 = blockIdx.x * RB;
+
+  int off[QP][4][DM];  // byte offset of the neighbour's replica vector within a state buffer
+  acc_t w[QP][4][DM];
+  acc_t inv[QP][4], hv[QP][4], s[QP][RB][4];
+#pragma unroll
+  for (int k = 0; k < QP; ++k) {
+    const int q = threadIdx.x + k * blockDim.x;
+    const bool own = q < Nq;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * q + v;  // < 4 Nq = Mp when own: inv_g and h_g hold Mp entries
+      const bool live = own && i < N;
+      inv[k][v] = own ? inv_g[i] : (acc_t)0;
+      hv[k][v] = own ? h_g[i] : (acc_t)0;
+#pragma unroll
+      for (int d = 0; d < DM; ++d) {
+        const bool e = live && d < D;
+        off[k][v][d] = e ? ell_col[(size_t)i * D + d] * (int)sizeof(V) : 0;
+        w[k][v][d] = e ? val[(size_t)i * D + d] : (acc_t)0;
+      }
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const int r = r0 + rr;
+        s[k][rr][v] = (a.load_state && live && r < a.R) ? state[(size_t)r * N + i] : (acc_t)0;
+      }
+    }
+    if (own) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        V y;
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) y.v[rr] = s[k][rr][v];
+        *reinterpret_cast<V*>(smem_sp + (4 * q + v) * (int)sizeof(V)) = y;
+      }
+    }
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int t = a.t_begin; t <= a.t_end; ++t) {
+    const acc_t coef_t = coef[t - 1];
+    const unsigned char* sc = smem_sp + (cur ? buf_bytes : 0);
+    unsigned char* sn = smem_sp + (cur ? 0 : buf_bytes);
+    const int k_rec = t - a.t_begin;
+#pragma unroll
+    for (int k = 0; k < QP; ++k) {
+      const int q = threadIdx.x + k * blockDim.x;
+      if (q >= Nq) continue;
+      acc_t acc[RB][4];
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[rr][v] = (acc_t)0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int d = 0; d < DM; ++d) {
+          const V x = *reinterpret_cast<const V*>(sc + off[k][v][d]);
+#pragma unroll
+          for (int rr = 0; rr < RB; ++rr) acc[rr][v] = fma_acc(w[k][v][d], x.v[rr], acc[rr][v]);
+        }
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr)
+        Epilogue<P>::apply(acc[rr], inv[k], hv[k], s[k][rr], a, coef_t, (uint32_t)q, (uint32_t)(r0 + rr),
+                           (uint32_t)t);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool live = 4 * q + v < N;
+        V y;
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) y.v[rr] = live ? s[k][rr][v] : (acc_t)0;
+        *reinterpret_cast<V*>(sn + (4 * q + v) * (int)sizeof(V)) = y;
+      }
+      if (traj && k_rec < a.record) {
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+          const int r = r0 + rr;
+          if (r >= a.R) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (4 * q + v < N) traj[((size_t)k_rec * a.R + r) * N + 4 * q + v] = s[k][rr][v];
+        }
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+#pragma unroll
+  for (int k = 0; k < QP; ++k) {
+    const int q = threadIdx.x + k * blockDim.x;
+    if (q >= Nq) continue;
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int r = r0 + rr;
+      if (r >= a.R) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * q + v;
+        if (i >= N) continue;
+        state[(size_t)r * N + i] = s[k][rr][v];
+        if (a.spins) a.spins[(size_t)r * N + i] = (s[k][rr][v] >= (acc_t)0) ? (int8_t)1 : (int8_t)-1;
+      }
     }
   }
 }
@@ -712,17 +855,116 @@ size_t sparse_lds_bytes(int prec, int N, int RB) {
   return (size_t)2 * 4 * ((N + 3) / 4) * RB * (prec == PREC_FP64 ? 8 : 4);
 }
 
+// Register-ELL variants: RB replicas per thread (4, 2, 1), DM = D rounded up to 4 / 8 / 16,
+// QP quads per thread (1 up to 512 quads, 2 up to 1024), with QP * DM * (value words + 1) <= 32.
+// FP64 keeps RB <= 2, and RB = 2 only for DM = 4, QP = 1: its epilogue, unrolled over the
+// replicas, would spill otherwise.
+template <int P, int RB>
+static const void* rq_fn_d(int DM, int QP) {
+  if (QP == 1) {
+    if (DM == 4) return (const void*)anneal_sparse_rq<P, RB, 4, 1>;
+    if (DM == 8) return (const void*)anneal_sparse_rq<P, RB, 8, 1>;
+    if constexpr (P != PREC_FP64)
+      if (DM == 16) return (const void*)anneal_sparse_rq<P, RB, 16, 1>;
+  } else if (QP == 2) {
+    if (DM == 4) return (const void*)anneal_sparse_rq<P, RB, 4, 2>;
+    if constexpr (P != PREC_FP64)
+      if (DM == 8) return (const void*)anneal_sparse_rq<P, RB, 8, 2>;
+  }
+  return nullptr;
+}
+
+static const void* rq_fn(int prec, int RB, int DM, int QP) {
+  if (prec == PREC_FP64) {
+    if (RB == 2) return DM == 4 && QP == 1 ? (const void*)anneal_sparse_rq<PREC_FP64, 2, 4, 1> : nullptr;
+    return RB == 1 ? rq_fn_d<PREC_FP64, 1>(DM, QP) : nullptr;
+  }
+  if (RB == 4) return rq_fn_d<PREC_FP32, 4>(DM, QP);
+  if (RB == 2) return rq_fn_d<PREC_FP32, 2>(DM, QP);
+  return RB == 1 ? rq_fn_d<PREC_FP32, 1>(DM, QP) : nullptr;
+}
+
+struct SparseRq {
+  const void* fn;
+  int RB, threads;
+  size_t lds;
+};
+
+// Picks the variant for (prec, N, D, R): the largest RB whose state fits in LDS and whose grid
+// still covers every CU (RB = 1 when none does); then RB = 4 gives way to RB = 2 when it leaves
+// the CUs under 16 resident waves and two RB = 2 workgroups fit on a CU (more waves hide the LDS
+// and transcendental latencies better than a third and fourth replica per thread). Returns 0
+// where the generic kernel must run.
+static int sparse_rq_pick(int prec, int N, int D, int R, SparseRq* o) {
+  const int Nq = (N + 3) / 4;
+  const int QP = Nq <= 512 ? 1 : (Nq <= 1024 ? 2 : 0);
+  const int DM = D <= 4 ? 4 : (D <= 8 ? 8 : (D <= 16 ? 16 : 0));
+  if (!QP || !DM || QP * DM * (prec == PREC_FP64 ? 3 : 2) > 32) return 0;
+  int dev = 0, cus = 256, max_lds = 65536;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  }
+  const size_t word = prec == PREC_FP64 ? 8 : 4;
+  const int threads = ((Nq + QP - 1) / QP + 63) / 64 * 64;
+  auto lds_of = [&](int rb) { return (size_t)2 * 4 * Nq * rb * word; };
+  auto fits = [&](int rb) { return lds_of(rb) <= (size_t)max_lds && rq_fn(prec, rb, DM, QP) != nullptr; };
+  auto per_cu = [&](int rb) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rq_fn(prec, rb, DM, QP), threads, lds_of(rb)) != hipSuccess)
+      return 0;
+    return nb;
+  };
+  int RB = 0;
+  for (int rb : {4, 2, 1}) {
+    if (!fits(rb)) continue;
+    RB = rb;
+    if ((R + rb - 1) / rb >= cus) break;
+  }
+  if (!RB) return 0;
+  if (RB == 4 && fits(2)) {
+    const int g4 = (R + 3) / 4, g2 = (R + 1) / 2, waves = threads / 64;
+    const long res4 = (long)std::min(g4, cus * std::max(per_cu(4), 1)) * waves;
+    if (res4 < 16L * cus && g2 >= 2 * cus && per_cu(2) >= 2) RB = 2;
+  }
+  o->fn = rq_fn(prec, RB, DM, QP);
+  o->RB = RB;
+  o->threads = threads;
+  o->lds = lds_of(RB);
+  return o->fn != nullptr;
+}
+
+int sparse_rq_applies(int prec, int N, int D) {
+  SparseRq c;
+  return sparse_rq_pick(prec, N, D, 1, &c);
+}
+
 hipError_t launch_anneal_sparse(int prec, const AnnealArgs& a, const int* ell_col, const void* ell_val, int D,
-                                int RB, hipStream_t st) {
+                                int RB, int allow_rq, int* used_rq, hipStream_t st) {
+  SparseRq c;
+  const bool rq = allow_rq && sparse_rq_pick(prec, a.N, D, a.R, &c);
+  if (used_rq) *used_rq = rq ? 1 : 0;
+  if (rq) {
+    hipError_t e = hipFuncSetAttribute(c.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+    if (e != hipSuccess) return e;
+    AnnealArgs args = a;
+    const void* col = ell_col;
+    const void* val = ell_val;
+    int d = D;
+    void* kargs[] = {&args, &col, &val, &d};
+    return hipLaunchKernel(c.fn, dim3((a.R + c.RB - 1) / c.RB), dim3(c.threads), kargs, c.lds, st);
+  }
   const int grid = (a.R + RB - 1) / RB;
   const size_t lds = sparse_lds_bytes(prec, a.N, RB);
   const void* fn = prec == PREC_FP64 ? (const void*)anneal_sparse<PREC_FP64> : (const void*)anneal_sparse<PREC_FP32>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  // 16 waves per workgroup (4 per SIMD; 8 waves in FP64, whose epilogue needs more registers): the
+  // gathers and the epilogue of one wave hide behind the others
   if (prec == PREC_FP64)
-    hipLaunchKernelGGL((anneal_sparse<PREC_FP64>), dim3(grid), dim3(256), lds, st, a, ell_col, ell_val, D, RB);
+    hipLaunchKernelGGL((anneal_sparse<PREC_FP64>), dim3(grid), dim3(512), lds, st, a, ell_col, ell_val, D, RB);
   else
-    hipLaunchKernelGGL((anneal_sparse<PREC_FP32>), dim3(grid), dim3(256), lds, st, a, ell_col, ell_val, D, RB);
+    hipLaunchKernelGGL((anneal_sparse<PREC_FP32>), dim3(grid), dim3(1024), lds, st, a, ell_col, ell_val, D, RB);
   return hipGetLastError();
 }
 

@@ -34,7 +34,8 @@ FLAG_FORCE_XCD = 0x8
 FLAG_FORCE_FENCED = 0x10
 FLAG_FORCE_LDS_J = 0x20
 FLAG_FORCE_SPARSE = 0x40
-PATHS = ("persistent", "step", "xcd", "xcd_fenced", "xcd_rj", "xcd_rj_fenced", "sparse")
+FLAG_SPARSE_GENERIC = 0x80
+PATHS = ("persistent", "step", "xcd", "xcd_fenced", "xcd_rj", "xcd_rj_fenced", "sparse", "sparse_rq")
 J_FORMATS = ("bf16", "fp8_e4m3", "fp4_e2m1", "native", "ell")
 
 # Every function declared in include/nmfa.h (checked by the CPU tests against the header).
@@ -161,7 +162,7 @@ class Solver:
                  knots: Optional[Sequence[Tuple[float, float]]] = None, record_iters: int = 0,
                  negate_noise: bool = False, upper_triangular: bool = False,
                  force_step: bool = False, force_xcd: bool = False, force_fenced: bool = False,
-                 force_lds_j: bool = False, force_sparse: bool = False):
+                 force_lds_j: bool = False, force_sparse: bool = False, sparse_generic: bool = False):
         J = np.ascontiguousarray(J, dtype=np.float64)
         if J.ndim != 2 or J.shape[0] != J.shape[1]:
             raise ValueError("J must be a square matrix")
@@ -188,6 +189,8 @@ class Solver:
             flags |= FLAG_FORCE_LDS_J
         if force_sparse:
             flags |= FLAG_FORCE_SPARSE
+        if sparse_generic:
+            flags |= FLAG_SPARSE_GENERIC
         p.flags = flags
         if knots is not None:
             ku = np.ascontiguousarray([k[0] for k in knots], dtype=np.float64)
