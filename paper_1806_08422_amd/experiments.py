@@ -13,8 +13,13 @@ here compares against the paper's numbers.
 * ``table1`` -- Table I: mean and best MAX-CUT value over 100 runs on 2000-spin instances: a
   random graph with 19,990 unit edges (the G22 class), a scale-free Barabasi-Albert graph with
   about 12,000 unit edges (the G39 class) and a complete graph with +-1 weights (K2000 class).
+* ``sweep`` -- the method's own parameters (Sec. II: alpha = sigma = 0.15 and the schedule of
+  Fig. 2 were tuned coarsely): success probability over a grid of damping alpha and noise sigma
+  (sigma = 0 is plain mean-field annealing, Sec. I) and over schedule variants, on SK instances.
+  An instance's target is the best energy seen in any sample of any variant, so the variants
+  are compared against one target.
 
-Usage: python -m paper_1806_08422_amd.experiments {fig3,fig4,table1} [--out FILE.json]
+Usage: python -m paper_1806_08422_amd.experiments {fig3,fig4,table1,sweep} [--out FILE.json]
 """
 from __future__ import annotations
 
@@ -58,17 +63,17 @@ def _tts99(t_sample, p):
     return t_sample * math.log(0.01) / math.log(1 - p)
 
 
-def fig4(sizes=(20, 40, 60, 80, 100), samples=10000, t_f=1000, precision="bf16"):
+def fig4(sizes=(20, 40, 60, 80, 100), samples=10000, t_f=1000, precision="bf16", counts=(10, 10, 20)):
     classes = {
-        "sk": (10, lambda n, k: instances.sk(n, 100 + k)),
-        "dense_maxcut": (10, lambda n, k: instances.gnp(n, 0.5, 200 + k)),
-        "degree3_maxcut": (20, lambda n, k: instances.random_regular(n, 3, 300 + k)),
+        "sk": (counts[0], lambda n, k: instances.sk(n, 100 + k)),
+        "dense_maxcut": (counts[1], lambda n, k: instances.gnp(n, 0.5, 200 + k)),
+        "degree3_maxcut": (counts[2], lambda n, k: instances.random_regular(n, 3, 300 + k)),
     }
     out = {}
     for name, (count, make) in classes.items():
         rows = []
         for n in sizes:
-            ps, tts = [], []
+            ps, tts, best = [], [], []
             for k in range(count):
                 inst = make(n, k)
                 with nmfa.Solver(inst.J, inst.h, precision=precision) as s:
@@ -78,12 +83,45 @@ def fig4(sizes=(20, 40, 60, 80, 100), samples=10000, t_f=1000, precision="bf16")
                     dt = time.perf_counter() - t0
                 p = float(np.mean(E <= E.min()))
                 ps.append(p)
+                best.append(float(E.min()))
                 tts.append(_tts99(dt / samples, p))
             rows.append({"n": n, "success_median": float(np.median(ps)),
                          "success_iqr": [float(np.percentile(ps, 25)), float(np.percentile(ps, 75))],
-                         "tts99_median_s": float(np.median(tts))})
+                         "tts99_median_s": float(np.median(tts)), "success": ps, "best_energy": best})
         out[name] = rows
     return {"samples_per_instance": samples, "t_f": t_f, "precision": precision, "classes": out}
+
+
+# schedule variants for the sweep: (u, T) knots, T interpolated geometrically between knots
+SCHEDULES = {
+    "paper (Fig. 2)": None,
+    "one geometric ramp 10 -> 0.05": ((0.0, 10.0), (1.0, 0.05)),
+    "cold start 2 -> 0.05": ((0.0, 2.0), (0.6, 0.5), (1.0, 0.05)),
+    "constant T = 0.5": ((0.0, 0.5), (1.0, 0.5)),
+}
+
+
+def sweep(n=100, count=5, samples=10000, t_f=1000, precision="bf16", alphas=(0.05, 0.1, 0.15, 0.3, 0.6),
+          sigmas=(0.0, 0.05, 0.15, 0.3, 0.5), schedules=SCHEDULES):
+    variants = [("grid", a, sg, "paper (Fig. 2)") for a in alphas for sg in sigmas]
+    variants += [("schedule", 0.15, 0.15, name) for name in schedules if name != "paper (Fig. 2)"]
+    energies = {}  # (variant index, instance) -> energies of all samples
+    for k in range(count):
+        inst = instances.sk(n, 400 + k)
+        for v, (_, a, sg, sched) in enumerate(variants):
+            with nmfa.Solver(inst.J, inst.h, precision=precision, alpha=a, sigma=sg, knots=schedules[sched]) as s:
+                s.anneal(samples, t_f, 9000 + k)
+                energies[(v, k)] = s.energies()[0]
+    target = [min(float(energies[(v, k)].min()) for v in range(len(variants))) for k in range(count)]
+    rows = []
+    for v, (kind, a, sg, sched) in enumerate(variants):
+        ps = [float(np.mean(energies[(v, k)] <= target[k])) for k in range(count)]
+        rows.append({"kind": kind, "alpha": a, "sigma": sg, "schedule": sched,
+                     "success_median": float(np.median(ps)), "success": ps,
+                     "mean_energy": float(np.mean([energies[(v, k)].mean() for k in range(count)])),
+                     "distinct_energies_max": int(max(len(np.unique(energies[(v, k)])) for k in range(count)))})
+    return {"n": n, "instances": count, "samples_per_instance": samples, "t_f": t_f, "precision": precision,
+            "targets": target, "variants": rows}
 
 
 def _ba_graph(n, m, seed):
@@ -121,14 +159,15 @@ def table1(runs=100, t_f=5000, precision="fp8j_bf16s"):
             s.anneal(runs, t_f, 777)
             cuts = s.cuts()
             path = s.info()["path"]
+        W = np.triu(J, 1)
         out[name] = {"mean_cut": float(cuts.mean()), "best_cut": float(cuts.max()), "runs": runs,
-                     "edges_weight": float(np.triu(J, 1).sum()), "kernel_path": path}
+                     "edges_weight": float(W.sum()), "positive_weight": float(W[W > 0].sum()), "kernel_path": path}
     return {"t_f": t_f, "precision": precision, "instances": out}
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("experiment", choices=["fig3", "fig4", "table1"])
+    ap.add_argument("experiment", choices=["fig3", "fig4", "table1", "sweep"])
     ap.add_argument("--out", default=None)
     ap.add_argument("--samples", type=int, default=10000)
     args = ap.parse_args(argv)
@@ -136,6 +175,8 @@ def main(argv=None):
         res = fig3()
     elif args.experiment == "fig4":
         res = fig4(samples=args.samples)
+    elif args.experiment == "sweep":
+        res = sweep(samples=args.samples)
     else:
         res = table1()
     text = json.dumps(res)
