@@ -403,7 +403,7 @@ def main() -> int:
             int(args.serving_budget_gib * (1 << 30)))
 
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(inst, T_F, R_sample=16, target_s=args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(inst, T_F, R_sample=32, target_s=args.cpu_seconds)
     solver.close()
     print(json.dumps(result), flush=True)
     return 0
