@@ -187,6 +187,35 @@ __device__ __forceinline__ bool xcd_group_wait(const XcdArgs& x, unsigned* bar, 
   return ld_dev(&ctl[CTL_ABORT]) != 0;
 }
 
+// Wait of the register-J kernel, which keeps the round trips to L2 off its critical path: the
+// caller polls the counter once ahead (seen, read while it draws the next noise), the polling
+// thread reads the abort word only every 64 polls, and its decision reaches the other waves
+// through an LDS word (abort_word) rather than a load of the control block by every thread.
+// Every wave of the workgroup therefore sees the same decision.
+__device__ __forceinline__ bool xrj_group_wait(const XcdArgs& x, unsigned* bar, unsigned epoch, bool xcd_mode,
+                                               int tid, unsigned seen, unsigned* abort_word) {
+  unsigned* ctl = x.ctl;
+  if (tid == 0) {
+    const unsigned target = (unsigned)x.P * epoch;
+    unsigned ab = 0;
+    if (seen < target) {
+      unsigned spins = 0;
+      while (ld_dev(bar) < target) {
+        if ((++spins & 63u) == 0 && (spins > SPIN_LIMIT || ld_dev(&ctl[CTL_ABORT]))) {
+          atomicExch(&ctl[CTL_ABORT], 1u);
+          ab = 1;
+          break;
+        }
+      }
+    }
+    if (!xcd_mode) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *abort_word = ab;
+  }
+  __syncthreads();
+  if (xcd_mode) asm volatile("buffer_inv sc0" ::: "memory");  // drop stale L1 lines
+  return *abort_word != 0;
+}
+
 __device__ __forceinline__ bool xcd_group_barrier(const XcdArgs& x, unsigned* bar, unsigned epoch,
                                                   bool xcd_mode, int tid) {
   xcd_group_arrive(bar, xcd_mode, tid);
@@ -475,13 +504,14 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
 // rows of J (FP4, one 32-bit register per 8 couplings: 128 registers at Kp = 2048) for the whole
 // anneal. A workgroup covers 128 rows x 64 replicas, so each widened J fragment feeds four MFMAs
 // and the spin stream per CU is half that of the LDS-resident variant; the whole LDS is a ring of
-// 16 KB spin chunks, deep enough to keep ~96 KB of loads in flight. The k loop is unrolled over
+// 16 KB spin chunks, of which XRJ_LA are loaded ahead of the one being read. The k loop is unrolled over
 // all chunks, which makes every register index, buffer index, wait count and load offset a
 // compile-time constant.
 constexpr int XRJ_ROWS = 128;                  // rows of J per workgroup (32 per wave)
 constexpr int XRJ_RG = 64;                     // replicas per group
 constexpr int XRJ_KC = 128;                    // k per spin chunk (four 32-k MFMA steps)
 constexpr int XRJ_NB = 8;                      // spin chunk buffers in LDS
+constexpr int XRJ_LA = 4;                      // chunks in flight ahead of the one being read
 constexpr int XRJ_CHB = XRJ_RG * XRJ_KC * 2;   // bytes of one chunk: 64 replicas x 128 k, BF16
 
 template <class F, int... I>
@@ -495,9 +525,10 @@ template <int NCH, int RT>
 __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
     AnnealArgs a, XcdArgs x) {
   extern __shared__ __align__(16) unsigned char smem[];  // XRJ_NB chunk buffers
+  __shared__ unsigned abort_word;                        // the group barrier's decision
   constexpr int NB = XRJ_NB;
   constexpr int DPW = 2 * RT;  // 1 KB direct-to-LDS loads per wave and chunk (16 KB over 8 / RT waves)
-  static_assert(DPW * (NB - 3) <= 63, "ring geometry");
+  static_assert(DPW * (XRJ_LA - 1) <= 63, "wait counts fit the vmcnt field");
   const int N = a.N, ks = x.ks;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g4 = lane >> 4, c = lane & 15;
@@ -565,16 +596,28 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
   // sigma * z for this lane's 4 x (4 RT) spins of iteration tt (noise does not depend on the state,
   // so it is drawn ahead: while the group barrier of the previous iteration completes)
   float zn[RT][4][4];
-  auto draw_noise = [&](int tt) {
+  // column tiles ct0 .. ct0 + 1 of the draw
+  auto draw_noise_half = [&](int tt, int ct0) {
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
+    for (int ct = ct0; ct < ct0 + 2; ++ct)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
         sigma_gauss4_f32(philox4x32_10((uint32_t)(row0[rt] >> 2), (uint32_t)(rgroup0 + 16 * ct + c), (uint32_t)tt, 0u,
                                        a.key0, a.key1),
                          neg2ln2_s2, zn[rt][ct]);
   };
-  draw_noise(a.t_begin);
+  // keeps the values of column tiles ct0, ct0 + 1 where they are: the empty volatile statements
+  // read them, so the draw cannot be moved past the code that follows
+  auto pin_noise_half = [&](int ct0) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = ct0; ct < ct0 + 2; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(zn[rt][ct][v]));
+  };
+  draw_noise_half(a.t_begin, 0);
+  draw_noise_half(a.t_begin, 2);
 
   // Spin fragments: replica q = 16*ct + c of the chunk, 16-byte unit u = 4*g4 + kq of its 256-byte
   // row, stored at unit u ^ (q & 15). A ds_read_b128 serves 16 lanes per cycle; their 16 replicas
@@ -634,8 +677,12 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
 
-    // prologue: the first NB - 1 chunks in flight, wait for chunk 0, read its first k step
-    constexpr int PRO = NB - 1 < NCH ? NB - 1 : NCH;
+    // prologue: the first XRJ_LA chunks in flight, wait for chunk 0, read its first k step. A
+    // deeper prologue only stalls the waves: the direct-to-LDS loads move about 54 bytes per
+    // cycle per CU, so issuing NB - 1 chunks at once holds the waves for about as long as the
+    // transfers take, while chunk 0 alone would already have landed.
+    constexpr int PRO = XRJ_LA < NCH ? XRJ_LA : NCH;
+    static_assert(XRJ_LA <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
 #pragma unroll
     for (int q = 0; q < PRO; ++q) issue(q, q);
     wait_vm<DPW * (PRO - 1)>();
@@ -644,18 +691,19 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
     // k step ks: the spins of step ks+1 are read into the other register set while the MFMAs
     // of step ks run. Before the first read of chunk c+1 (in the last step of chunk c) the
     // workgroup meets at a barrier: chunk c+1 has landed for every wave, and every wave is done
-    // reading chunk c-1, whose buffer then receives chunk c+NB-1.
+    // reading chunk c-1. Chunk c+XRJ_LA then goes to buffer (c+XRJ_LA) % NB, which last held
+    // chunk c+XRJ_LA-NB <= c-1.
     static_for(
         [&](auto kqc) {
           constexpr int kstep = decltype(kqc)::value;
           constexpr int ch = kstep >> 2;
           if constexpr ((kstep & 3) == 3 && ch + 1 < NCH) {
-            constexpr int last_issued = (ch + NB - 2 < NCH - 1) ? ch + NB - 2 : NCH - 1;
+            constexpr int last_issued = (ch + XRJ_LA - 1 < NCH - 1) ? ch + XRJ_LA - 1 : NCH - 1;
             wait_vm<DPW * (last_issued - (ch + 1))>();
             __builtin_amdgcn_sched_barrier(0);
             bare_barrier();
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (ch + NB - 1 < NCH) issue(ch + NB - 1, (ch + NB - 1) % NB);
+            if constexpr (ch + XRJ_LA < NCH) issue(ch + XRJ_LA, (ch + XRJ_LA) % NB);
           }
           // The reads of step kstep (issued a step ago) are complete by now; waiting for them before
           // issuing those of step kstep+1 keeps the MFMAs below free of any LDS wait.
@@ -702,18 +750,20 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
     }
 
     if (t < a.t_end) {
+      // Arrive, draw the next iteration's noise (it does not depend on the state) and wait. The
+      // draw is pinned between arrival and wait, or the compiler would sink it past the wait onto
+      // the critical path; halfway through, the polling thread reads the group counter once, so
+      // that the round trip of that read overlaps the second half of the draw.
       xcd_group_arrive(bar, xcd_mode, tid);
-      draw_noise(t + 1);
-      // Pin the draw between arrival and wait: the values are only used in the next iteration, so
-      // the compiler would otherwise sink the draw past the wait onto the critical path. An empty
-      // volatile statement that reads each value cannot move across the wait's synchronisation.
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(zn[rt][ct][v]));
-      aborted = xcd_group_wait(x, bar, (unsigned)++epoch, xcd_mode, tid);
+      draw_noise_half(t + 1, 0);
+      pin_noise_half(0);
+      unsigned seen = 0;
+      __builtin_amdgcn_sched_barrier(0);
+      if (tid == 0) seen = ld_dev(bar);
+      __builtin_amdgcn_sched_barrier(0);
+      draw_noise_half(t + 1, 2);
+      pin_noise_half(2);
+      aborted = xrj_group_wait(x, bar, (unsigned)++epoch, xcd_mode, tid, seen, &abort_word);
     }
   }
 
