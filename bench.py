@@ -12,8 +12,9 @@ timing starts.
 Prints ONE JSON line. Metric: spin-updates/s = N * R * t_f / (seconds per anneal). Alongside:
 the FP64 GPU path on the same workload (speed-up), TTS99 at N=2000 and N=100, the N=100 dense
 MAX-CUT timing workload of the paper (time per sample), a random 3-regular MAX-CUT instance at
-N=2000 on the sparse kernel against the dense kernel, the roofline of the dominant kernel and the
-CPU oracle timed on a bounded sample.
+N=2000 on the sparse kernel against the dense kernel, the N=100 Moebius ladder on the FP32 path
+(success at its closed-form ground energy) and SK N=20 on the FP64 path (success at the enumerated
+ground energy), the roofline of the dominant kernel and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -63,6 +64,20 @@ def measured_traffic(path: str):
     if fields.get("kernel_source_sha256", "").strip() != sha or fields.get("kernel_path", "").strip() != path:
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def ground_energy_enumerated(J: np.ndarray) -> float:
+    """Minimum of H(s) = sum_{i<j} J_ij s_i s_j over all s in {-1, +1}^n (h = 0, so s_0 = +1 is
+    enough by the symmetry H(s) = H(-s)), by enumeration in blocks; for n <= 24."""
+    n = J.shape[0]
+    best = math.inf
+    block = 1 << min(16, n - 1)
+    for start in range(0, 1 << (n - 1), block):
+        idx = np.arange(start, start + block, dtype=np.int64)
+        bits = (idx[:, None] >> np.arange(n - 1)) & 1
+        s = np.concatenate([np.ones((block, 1)), 1.0 - 2.0 * bits], axis=1)
+        best = min(best, float((0.5 * np.einsum("ri,ij,rj->r", s, J, s)).min()))
+    return best
 
 
 def measured_valu_instructions(path: str):
@@ -385,6 +400,31 @@ def main() -> int:
             "spin_updates_per_s": N * R * T_F / (msd3 * 1e-3),
             "dense_kernel_ms_per_anneal": wx[0], "speedup_vs_dense": wx[0] / msd3,
         }
+        # Moebius ladder N = 100 (ring plus chords, J = +1): FP32 path vs the FP64 path, success at
+        # the closed-form ground energy -3N/2 + 4 (N/2 even: two edges stay uncut)
+        ml = instances.moebius_ladder(100)
+        e0_ml = -1.5 * 100 + 4
+        with nmfa.Solver(ml.J, ml.h, precision="fp32") as s32, nmfa.Solver(ml.J, ml.h, precision="fp64") as s64:
+            w32, _ = timed_anneals(s32, 4096, 1000, [51, 52], stream)
+            w64, _ = timed_anneals(s64, 4096, 1000, [53], stream)
+            p32 = float(np.mean(s32.energies()[0] <= e0_ml))
+            p64 = float(np.mean(s64.energies()[0] <= e0_ml))
+        ms32 = float(min(w32))
+        se = math.sqrt(p32 * (1 - p32) / 4096 + p64 * (1 - p64) / 4096)
+        extra["moebius100_fp32"] = {
+            "R": 4096, "t_f": 1000, "ms_per_anneal": ms32, "spin_updates_per_s": 100 * 4096 * 1000 / (ms32 * 1e-3),
+            "fp64_ms_per_anneal": w64[0], "E_ground": e0_ml, "p_fp32": p32, "p_fp64": p64,
+            "z_diff": (p32 - p64) / se if se > 0 else 0.0,
+            "tts99_s_fp32": tts99(ms32 * 1e-3 / 4096, p32), "tts99_s_fp64": tts99(w64[0] * 1e-3 / 4096, p64),
+        }
+        # SK N = 20 on the FP64 path (R = 256, t_f = 1000): success at the enumerated ground energy
+        sk20 = instances.sk(20, 1)
+        e0_sk = ground_energy_enumerated(sk20.J)
+        with nmfa.Solver(sk20.J, sk20.h, precision="fp64") as s64:
+            w20, _ = timed_anneals(s64, 256, 1000, [61], stream)
+            p20 = float(np.mean(s64.energies()[0] <= e0_sk))
+        extra["sk20_fp64"] = {"R": 256, "t_f": 1000, "ms_per_anneal": w20[0], "E_ground": e0_sk, "p_fp64": p20,
+                              "tts99_s": tts99(w20[0] * 1e-3 / 256, p20)}
         mc = instances.gnp(100, 0.5, 1)
         with nmfa.Solver(mc.J, mc.h, precision="bf16") as sm:
             wm, _ = timed_anneals(sm, 10000, 1000, [31, 32, 33], stream)
