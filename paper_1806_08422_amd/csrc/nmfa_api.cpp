@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/nmfa.h"
@@ -112,6 +113,68 @@ static int fp4e2m1_code(double v) {
 }
 
 static bool is_integral(double v) { return std::isfinite(v) && v == std::floor(v) && std::fabs(v) < 9e15; }
+
+// The storage codes of coupling values (FP8 bits and value, FP4 code, BF16 bits), memoised by
+// bit pattern: an instance has few distinct couplings (often 0 and +-1), and the rounding
+// routines would otherwise run once per matrix element. Values beyond the first CAP distinct
+// ones are converted directly.
+// Runs f(lo, hi) over [0, n) split into contiguous ranges on up to 16 host threads (one range
+// for small n, where starting threads costs more than the pass).
+template <class F>
+static void parallel_rows(int n, F&& f) {
+  int T = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+  T = std::min(T, n / 128);
+  if (T <= 1) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(T);
+  for (int t = 0; t < T; ++t) {
+    const int lo = (int)((long)n * t / T), hi = (int)((long)n * (t + 1) / T);
+    th.emplace_back([&f, lo, hi] { f(lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
+
+struct CouplingCodes {
+  static constexpr int CAP = 16;
+  int n = 0;
+  uint64_t key[CAP];
+  uint8_t f8[CAP];
+  double f8v[CAP];
+  int f4[CAP];
+  uint16_t b16[CAP];
+  int slot(double v) {
+    uint64_t b;
+    std::memcpy(&b, &v, 8);
+    for (int k = 0; k < n; ++k)
+      if (key[k] == b) return k;
+    if (n == CAP) return -1;
+    key[n] = b;
+    f8[n] = fp8e4m3_bits(v);
+    f8v[n] = fp8e4m3_value(f8[n]);
+    f4[n] = fp4e2m1_code(v);
+    b16[n] = bf16_bits(v);
+    return n++;
+  }
+  uint8_t fp8(double v) {
+    const int k = slot(v);
+    return k >= 0 ? f8[k] : fp8e4m3_bits(v);
+  }
+  double fp8_value(double v) {
+    const int k = slot(v);
+    return k >= 0 ? f8v[k] : fp8e4m3_value(fp8e4m3_bits(v));
+  }
+  int fp4(double v) {
+    const int k = slot(v);
+    return k >= 0 ? f4[k] : fp4e2m1_code(v);
+  }
+  uint16_t bf16(double v) {
+    const int k = slot(v);
+    return k >= 0 ? b16[k] : bf16_bits(v);
+  }
+};
 
 // ------------------------------------------------------------------------------------------
 // Context
@@ -217,25 +280,70 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
       return fail(NMFA_EINVAL, "nmfa_create: knot positions must start at 0 and end at 1");
   }
 
-  // couplings: symmetrise if given as an upper triangle, validate
+  // couplings: symmetrise if given as an upper triangle (else J is used in place), validate
   const size_t nn = (size_t)n * n;
-  std::vector<double> Jf(nn);
   const bool upper = (p->flags & NMFA_FLAG_UPPER_TRIANGULAR) != 0;
-  for (int i = 0; i < n; ++i) {
-    for (int j = 0; j < n; ++j) {
-      double v;
-      if (upper) v = (i < j) ? J[(size_t)i * n + j] : (i > j ? J[(size_t)j * n + i] : 0.0);
-      else v = J[(size_t)i * n + j];
-      if (!std::isfinite(v)) return fail(NMFA_EINVAL, "nmfa_create: J[%d][%d] is not finite", i, j);
-      Jf[(size_t)i * n + j] = v;
+  std::vector<double> Jmirror;
+  if (upper) {
+    Jmirror.resize(nn);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        Jmirror[(size_t)i * n + j] = (i < j) ? J[(size_t)i * n + j] : (i > j ? J[(size_t)j * n + i] : 0.0);
+  }
+  const double* Jf = upper ? Jmirror.data() : J;
+  // one pass over the rows (on host threads) gathers what the checks and the set-up need:
+  // finiteness, integrality and magnitude, the exact storage formats, nonzeros per row, and
+  // h_i^2 + sum_j J_ij^2 summed in column order
+  const bool fp8j = p->precision == NMFA_FP8J_BF16S;
+  struct RowInfo {
+    int bad_j = -1, sym_j = -1, deg = 0, jmax = 0;
+    bool integral = true, fp8x = true, fp4x = true;
+    double sumsq = 0.0;
+  };
+  std::vector<RowInfo> rows(n);
+  parallel_rows(n, [&](int lo, int hi) {
+    CouplingCodes cc;
+    for (int i = lo; i < hi; ++i) {
+      RowInfo& r = rows[i];
+      const double* Ji = Jf + (size_t)i * n;
+      double acc = h ? h[i] * h[i] : 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double v = Ji[j];
+        if (!std::isfinite(v)) {
+          r.bad_j = j;
+          break;
+        }
+        acc += v * v;
+        if (v != 0.0) ++r.deg;
+        if (r.integral) {
+          if (is_integral(v)) r.jmax = std::max(r.jmax, (int)std::min(std::fabs(v), 1e9));
+          else r.integral = false;
+        }
+        if (r.fp8x || r.fp4x) {
+          const double w = fp8j ? cc.fp8_value(v) : v;
+          if (!fp8j && cc.fp8_value(w) != w) r.fp8x = false;
+          if (cc.fp4(w) < 0) r.fp4x = false;
+        }
+      }
+      r.sumsq = acc;
     }
-  }
-  for (int i = 0; i < n; ++i) {
+  });
+  for (int i = 0; i < n; ++i)
+    if (rows[i].bad_j >= 0) return fail(NMFA_EINVAL, "nmfa_create: J[%d][%d] is not finite", i, rows[i].bad_j);
+  for (int i = 0; i < n; ++i)
     if (Jf[(size_t)i * n + i] != 0.0) return fail(NMFA_EINVAL, "nmfa_create: J[%d][%d] != 0 (diagonal)", i, i);
-    for (int j = i + 1; j < n; ++j)
-      if (Jf[(size_t)i * n + j] != Jf[(size_t)j * n + i])
-        return fail(NMFA_EINVAL, "nmfa_create: J is not symmetric at (%d, %d)", i, j);
-  }
+  // symmetry in 64 x 64 tiles, so that the transposed reads stay in cache; each row keeps its
+  // first violation, so the first one in row-major order is reported
+  parallel_rows((n + 63) / 64, [&](int blo, int bhi) {
+    for (int ib = 64 * blo; ib < std::min(64 * bhi, n); ib += 64)
+      for (int jb = ib; jb < n; jb += 64)
+        for (int i = ib; i < std::min(ib + 64, n); ++i)
+          for (int j = std::max(jb, i + 1); j < std::min(jb + 64, n); ++j)
+            if (rows[i].sym_j < 0 && Jf[(size_t)i * n + j] != Jf[(size_t)j * n + i]) rows[i].sym_j = j;
+  });
+  for (int i = 0; i < n; ++i)
+    if (rows[i].sym_j >= 0)
+      return fail(NMFA_EINVAL, "nmfa_create: J is not symmetric at (%d, %d)", i, rows[i].sym_j);
   if (h)
     for (int i = 0; i < n; ++i)
       if (!std::isfinite(h[i])) return fail(NMFA_EINVAL, "nmfa_create: h[%d] is not finite", i);
@@ -262,12 +370,9 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   if (!any_h) c->h.clear();
   c->J_integral = true;
   int Jmax = 0;
-  for (size_t k = 0; k < nn; ++k) {
-    if (!is_integral(Jf[k])) {
-      c->J_integral = false;
-      break;
-    }
-    Jmax = std::max(Jmax, (int)std::min(std::fabs(Jf[k]), 1e9));
+  for (int i = 0; i < n; ++i) {
+    c->J_integral = c->J_integral && rows[i].integral;
+    Jmax = std::max(Jmax, rows[i].jmax);
   }
   const bool use_J8 = c->J_integral && Jmax <= 127;
   for (int i = 0; i < n; ++i)
@@ -278,10 +383,9 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   const bool bf = (c->prec == NMFA_BF16 || c->prec == NMFA_FP8J_BF16S);
   // exact formats of the couplings the MFMA consumes (FP8-rounded for the FP8-J precision)
   bool j_fp8_exact = true, j_fp4_exact = true;
-  for (size_t k = 0; k < nn && (j_fp8_exact || j_fp4_exact); ++k) {
-    const double v = (c->prec == NMFA_FP8J_BF16S) ? fp8e4m3_value(fp8e4m3_bits(Jf[k])) : Jf[k];
-    if (c->prec != NMFA_FP8J_BF16S && fp8e4m3_value(fp8e4m3_bits(v)) != v) j_fp8_exact = false;
-    if (fp4e2m1_code(v) < 0) j_fp4_exact = false;
+  for (int i = 0; i < n; ++i) {
+    j_fp8_exact = j_fp8_exact && rows[i].fp8x;
+    j_fp4_exact = j_fp4_exact && rows[i].fp4x;
   }
   const int Mp_s = (int)round_up(n, 16);
   const int Kp_s = (int)round_up(n, bf ? 32 : 16);
@@ -299,11 +403,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   const bool x_rj = x_ok && x_jfmt == 2 && xrj_fits(n) && !(p->flags & NMFA_FLAG_FORCE_LDS_J);
   // sparse (ELL) kernel: maximum degree D <= 64 and the workgroup's state fits in LDS
   int deg_max = 0;
-  for (int i = 0; i < n; ++i) {
-    int d = 0;
-    for (int j = 0; j < n; ++j) d += (Jf[(size_t)i * n + j] != 0.0) ? 1 : 0;
-    deg_max = std::max(deg_max, d);
-  }
+  for (int i = 0; i < n; ++i) deg_max = std::max(deg_max, rows[i].deg);
   const int sp_prec = (c->prec == NMFA_FP64) ? 0 : 1;  // kernel arithmetic: FP64 or FP32
   int sp_rb = 0;
   for (int rb : {8, 4, 2, 1})
@@ -370,9 +470,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   std::vector<double> inv(Mp, 0.0), hterm(Mp, 0.0);
   for (int i = 0; i < n; ++i) {
     const double hi = any_h ? h[i] : 0.0;
-    double acc = hi * hi;
-    for (int j = 0; j < n; ++j) acc += Jf[(size_t)i * n + j] * Jf[(size_t)i * n + j];
-    const double nrm = std::sqrt(acc);
+    const double nrm = std::sqrt(rows[i].sumsq);
     inv[i] = nrm > 0.0 ? 1.0 / nrm : 0.0;
     hterm[i] = (c->prec == NMFA_FP64) ? hi : hi * inv[i];
   }
@@ -387,15 +485,17 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   else if (jfmt2 == 2) jbytes = (size_t)Mp * Kp / 2;
   else jbytes = (size_t)Mp * Kp * (jfmt2 == 0 ? 2 : es);
   std::vector<unsigned char> jbuf(jbytes, 0);
-  for (int i = 0; i < n && jbytes; ++i) {
+  if (jbytes) parallel_rows(n, [&](int lo, int hi) {
+  CouplingCodes codes;
+  for (int i = lo; i < hi; ++i) {
     for (int j = 0; j < n; ++j) {
       double v = Jf[(size_t)i * n + j];
-      if (c->prec == NMFA_FP8J_BF16S) v = fp8e4m3_value(fp8e4m3_bits(v));
+      if (c->prec == NMFA_FP8J_BF16S) v = codes.fp8_value(v);
       const size_t idx = (size_t)i * Kp + j;
       if (j8_small || jfmt2 == 1) {
-        jbuf[idx] = fp8e4m3_bits(v);
+        jbuf[idx] = codes.fp8(v);
       } else if (jfmt2 == 2) {
-        const uint8_t code = (uint8_t)fp4e2m1_code(v);
+        const uint8_t code = (uint8_t)codes.fp4(v);
         jbuf[idx / 2] |= (uint8_t)((idx & 1) ? (code << 4) : code);
       } else if (c->prec == NMFA_FP64) {
         std::memcpy(&jbuf[idx * 8], &v, 8);
@@ -403,11 +503,12 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
         const float f = (float)v;
         std::memcpy(&jbuf[idx * 4], &f, 4);
       } else {
-        const uint16_t bits = bf16_bits(v);
+        const uint16_t bits = codes.bf16(v);
         std::memcpy(&jbuf[idx * 2], &bits, 2);
       }
     }
   }
+  });
 
   auto cleanup_fail = [&](int code) {
     nmfa_destroy(c);
@@ -431,14 +532,16 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     const int D = c->ell_D;
     std::vector<int> col((size_t)n * D);
     std::vector<double> vd((size_t)n * D, 0.0);
-    for (int i = 0; i < n; ++i) {
+    parallel_rows(n, [&](int lo, int hi) {
+    CouplingCodes codes;
+    for (int i = lo; i < hi; ++i) {
       int d = 0;
       for (int j = 0; j < n; ++j) {
         double v = Jf[(size_t)i * n + j];
         if (v == 0.0) continue;
-        if (c->prec == NMFA_FP8J_BF16S) v = fp8e4m3_value(fp8e4m3_bits(v));
+        if (c->prec == NMFA_FP8J_BF16S) v = codes.fp8_value(v);
         else if (c->prec == NMFA_BF16) {
-          const uint32_t b = (uint32_t)bf16_bits(v) << 16;
+          const uint32_t b = (uint32_t)codes.bf16(v) << 16;
           float f;
           std::memcpy(&f, &b, 4);
           v = f;
@@ -449,6 +552,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
       }
       for (; d < D; ++d) col[(size_t)i * D + d] = i;
     }
+    });
     CREATE_TRY(hipMalloc(&c->d_ell_col, col.size() * sizeof(int)));
     CREATE_TRY(hipMemcpy(c->d_ell_col, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice));
     if (c->prec == NMFA_FP64) {
@@ -479,13 +583,16 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->Np8 = (int)round_up(n, 64);
     const size_t np = (size_t)c->Np8 * c->Np8;
     std::vector<int8_t> j8(np, 0);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) j8[(size_t)i * c->Np8 + j] = (int8_t)Jf[(size_t)i * n + j];
+    const int np8 = c->Np8;
+    parallel_rows(n, [&](int lo, int hi) {
+      for (int i = lo; i < hi; ++i)
+        for (int j = 0; j < n; ++j) j8[(size_t)i * np8 + j] = (int8_t)Jf[(size_t)i * n + j];
+    });
     CREATE_TRY(hipMalloc(&c->d_J8, np));
     CREATE_TRY(hipMemcpy(c->d_J8, j8.data(), np, hipMemcpyHostToDevice));
   } else {
     CREATE_TRY(hipMalloc(&c->d_J64, nn * 8));
-    CREATE_TRY(hipMemcpy(c->d_J64, Jf.data(), nn * 8, hipMemcpyHostToDevice));
+    CREATE_TRY(hipMemcpy(c->d_J64, Jf, nn * 8, hipMemcpyHostToDevice));
   }
   if (any_h) {
     CREATE_TRY(hipMalloc(&c->d_h, n * 8));

@@ -1,12 +1,18 @@
 // Continuous-batching annealing server (nmfa_server_* in include/nmfa.h).
 //
-// One scheduler thread owns a HIP stream. Requests wait in a FIFO queue; admission is by device
-// memory budget and a cap on concurrently admitted requests. Admitted requests are advanced in
-// rounds of chunk_iters iterations of Algorithm 1:
+// One scheduler thread owns four HIP streams. Requests wait in a FIFO queue; admission is by
+// device memory budget and a cap on concurrently admitted requests. Admitted requests are
+// advanced in rounds of chunk_iters iterations of Algorithm 1:
 //   * all admitted requests on the persistent small-N path share ONE launch per round
 //     (anneal_small_batched over every request's replica blocks; each workgroup reads its own
 //     request's arguments), so newly admitted work overlaps with running work on the device;
-//   * larger requests advance by the same chunk on their own kernels in the same round;
+//   * larger requests advance by the same chunk on their own kernels in the same round, on the
+//     other streams, so that their kernels run side by side with the batched launch and with
+//     each other. Requests on the persistent XCD-group kernels share one stream: the workgroups
+//     of such a launch wait for each other, and two of them side by side could each hold part
+//     of the chip the other needs. The sparse and per-iteration kernels never wait for other
+//     workgroups, so they spread over the remaining streams and at worst delay a group
+//     launch's start;
 //   * between rounds the spin state stays on the device (resuming is bit-exact), finished
 //     requests return their energies/spins and release their memory, and queued requests are
 //     admitted.
@@ -71,10 +77,13 @@ size_t job_bytes(int n, int R, int t_f, bool j_integral) {
 
 }  // namespace
 
+constexpr int SERVER_LANES = 3;  // streams besides the batched launch's (4 hardware queues in all)
+
 struct nmfa_server {
   nmfa_server_params p{};
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;            // the batched small-N launch
+  hipStream_t lanes[SERVER_LANES] = {};    // [0]: XCD-group kernels; [1..]: sparse, per-iteration
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Job*> queue;
@@ -249,11 +258,14 @@ void scheduler(nmfa_server* s) {
         for (Job* j : batched) ran.push_back(j);
       }
     }
+    int spread = 0;
+    std::vector<hipStream_t> stream_of(round_jobs.size(), s->stream);
     for (size_t k = 0; k < round_jobs.size() && rc == NMFA_OK; ++k) {
       Job* j = round_jobs[k];
       if (!j->ctx || j->ctx->path == 0) continue;
       const int te = t_end_of[k];
-      int r2 = ctx_launch_run(j->ctx, j->R, j->t_f, j->t_done + 1, te, j->seed, s->stream, false);
+      stream_of[k] = j->ctx->path == 2 ? s->lanes[0] : s->lanes[1 + (spread++ % (SERVER_LANES - 1))];
+      int r2 = ctx_launch_run(j->ctx, j->R, j->t_f, j->t_done + 1, te, j->seed, stream_of[k], false);
       if (r2 != NMFA_OK) {
         std::lock_guard<std::mutex> lk(s->mu);
         j->msg = nmfa_last_error();
@@ -268,11 +280,15 @@ void scheduler(nmfa_server* s) {
     for (Job* j : ran) {
       const size_t k = std::find(round_jobs.begin(), round_jobs.end(), j) - round_jobs.begin();
       if (t_end_of[k] == j->t_f) {
-        if (ctx_finish_run(j->ctx, s->stream) != NMFA_OK) rc = NMFA_EDEVICE;
+        if (ctx_finish_run(j->ctx, stream_of[k]) != NMFA_OK) rc = NMFA_EDEVICE;
         done.push_back(j);
       }
     }
-    const hipError_t se = hipStreamSynchronize(s->stream);
+    hipError_t se = hipStreamSynchronize(s->stream);
+    for (hipStream_t ls : s->lanes) {
+      const hipError_t e = hipStreamSynchronize(ls);
+      if (se == hipSuccess) se = e;
+    }
     ++s->st.rounds;
     std::lock_guard<std::mutex> lk(s->mu);
     if (rc != NMFA_OK || se != hipSuccess) {
@@ -324,7 +340,12 @@ extern "C" int nmfa_server_create(const nmfa_server_params* p, nmfa_server** out
     return nmfa_fail(NMFA_EINVAL, "nmfa_server_create: invalid parameters");
   nmfa_server* s = new nmfa_server();
   s->p = *p;
-  if (hipGetDevice(&s->device) != hipSuccess || hipStreamCreate(&s->stream) != hipSuccess) {
+  bool ok = hipGetDevice(&s->device) == hipSuccess && hipStreamCreate(&s->stream) == hipSuccess;
+  for (hipStream_t& ls : s->lanes) ok = ok && hipStreamCreate(&ls) == hipSuccess;
+  if (!ok) {
+    for (hipStream_t ls : s->lanes)
+      if (ls) (void)hipStreamDestroy(ls);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return nmfa_fail(NMFA_EDEVICE, "nmfa_server_create: no HIP device / stream");
   }
@@ -477,5 +498,6 @@ extern "C" void nmfa_server_destroy(nmfa_server* s) {
   (void)hipFree(s->d_jobs);
   (void)hipFree(s->d_tasks);
   (void)hipStreamDestroy(s->stream);
+  for (hipStream_t ls : s->lanes) (void)hipStreamDestroy(ls);
   delete s;
 }

@@ -58,6 +58,23 @@ def test_rejects_diagonal_and_nan():
     assert _create_rc(np.zeros((3, 3)), np.array([0.0, np.inf, 0.0]))[0] == -1
 
 
+def test_validation_names_the_first_offender_at_large_n():
+    # n = 600 runs the checks on several host threads; the first violation in row-major order is
+    # reported all the same
+    import instances
+
+    J = instances.sk(600, 3).J.copy()
+    J[300, 450] += 1.0   # pair (300, 450) asymmetric
+    J[400, 20] += 2.0    # pair (20, 400) asymmetric: first in row-major order
+    code, msg = _create_rc(J)
+    assert code == -1 and "symmetric at (20, 400)" in msg
+    J = instances.sk(600, 3).J.copy()
+    J[100, 7] = J[7, 100] = np.nan
+    J[50, 590] = J[590, 50] = np.inf
+    code, msg = _create_rc(J)
+    assert code == -1 and "J[7][100] is not finite" in msg  # (7, 100) precedes (50, 590)
+
+
 def test_rejects_bad_parameters_and_schedules():
     J = np.zeros((4, 4))
     assert _create_rc(J, alpha=0.0)[0] == -1
