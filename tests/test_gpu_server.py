@@ -104,3 +104,29 @@ def test_cancel_queued_and_running(nmfa):
         t3 = srv.submit(small.J, small.h, 64, 100, 3)
         assert srv.wait(t3, 60000) and srv.poll(t3) == nmfa.JOB_DONE
         assert srv.stats()["cancelled"] == 2
+
+
+def test_large_jobs_side_by_side(nmfa):
+    # dense group-kernel jobs (one stream), sparse jobs (two streams) and small batched jobs in the
+    # same rounds: each result is the one the job gets alone, bit for bit
+    specs = [("sk", 500, 96, 400), ("sk", 900, 128, 300), ("sk", 1300, 64, 350),
+             ("reg", 600, 200, 380), ("reg", 1100, 64, 420), ("reg", 1500, 130, 300),
+             ("sk", 120, 80, 300), ("reg", 200, 50, 360)]
+    jobs = []
+    for k, (kind, n, R, t_f) in enumerate(specs):
+        inst = instances.sk(n, 60 + k) if kind == "sk" else instances.random_regular(n, 3 + k % 4, 70 + k)
+        jobs.append((inst, R, t_f, 8100 + k))
+    alone, paths = [], []
+    for inst, R, t_f, seed in jobs:
+        with nmfa.Solver(inst.J, inst.h, precision="bf16") as s:
+            s.anneal(R, t_f, seed)
+            alone.append(s.energies()[0])
+            paths.append(s.info()["path"])
+    assert {"xcd_rj", "xcd_rj_fenced"} & set(paths) and {"sparse_rq"} & set(paths) and "persistent" in paths
+    with nmfa.Server(precision="bf16", max_active=64, chunk_iters=100) as srv:
+        tickets = [srv.submit(inst.J, inst.h, R, t_f, seed) for inst, R, t_f, seed in jobs]
+        for E, t in zip(alone, tickets):
+            assert srv.wait(t, 120000)
+            assert np.array_equal(srv.result(t)["E"], E)
+        st = srv.stats()
+        assert st["completed"] == len(jobs) and st["failed"] == 0
