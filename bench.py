@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 # MI355X published peaks
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP8_TFLOPS = 5000.0
 PEAK_HBM_GBS = 8000.0
 # Vector ALU issue peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
 # (half the 157.3 TFLOP/s FP32 vector figure, which counts packed FMAs as 4 flops per lane)
@@ -217,9 +218,10 @@ def serving_leg(nmfa, instances_mod, n_burst: int, n_stream: int, budget_bytes: 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("g2000", "d3_2000"), default="g2000",
+    ap.add_argument("--workload", choices=("g2000", "d3_2000", "g2000_fp8s"), default="g2000",
                     help="g2000: dense G(2000, 0.5) MAX-CUT (default); d3_2000: random 3-regular "
-                         "MAX-CUT at N = 2000 on the sparse kernel")
+                         "MAX-CUT at N = 2000 on the sparse kernel; g2000_fp8s: the default workload "
+                         "with FP8 spin operands (precision fp8j_fp8s)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -247,12 +249,13 @@ def main() -> int:
     stream = torch.cuda.current_stream().cuda_stream
 
     N, R, T_F = 2000, 1024, 5000
-    dense = args.workload == "g2000"
+    dense = args.workload in ("g2000", "g2000_fp8s")
+    prec_main = "fp8j_fp8s" if args.workload == "g2000_fp8s" else "fp8j_bf16s"
     inst = instances.gnp(N, 0.5, 1) if dense else instances.random_regular(N, 3, 1)
     spin_updates = N * R * T_F
     flops_per_iter = 2.0 * N * N * R  # algorithmic: 2N flops per spin update (dense J)
 
-    solver = nmfa.Solver(inst.J, inst.h, precision="fp8j_bf16s")
+    solver = nmfa.Solver(inst.J, inst.h, precision=prec_main)
     for w in range(args.warmup):
         solver.anneal(R, T_F, 500 + w, stream)
     torch.cuda.synchronize()
@@ -279,11 +282,14 @@ def main() -> int:
     achieved_tflops = flops_per_launch / (kernel_ms * 1e-3) / 1e12
     value = spin_updates / (ms_per_step * 1e-3)
     if dense:
+        fp8s = prec_main == "fp8j_fp8s"
+        peak = PEAK_FP8_TFLOPS if fp8s else PEAK_BF16_TFLOPS
         workload = ("dense random-graph MAX-CUT G(2000,0.5), J in {0,1}, h=0, R=1024, t_f=5000, "
-                    "J rounded to FP8-E4M3 (exact here) / spins BF16 / FP32 accumulate")
+                    "J rounded to FP8-E4M3 (exact here) / spins " + ("FP8-E4M3" if fp8s else "BF16") +
+                    " / FP32 accumulate")
         roofline = {
-            "bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved_tflops / PEAK_BF16_TFLOPS, "traffic": measured_traffic(path),
+            "bound": "mfma", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved_tflops / peak, "traffic": None if fp8s else measured_traffic(path),
             "kernel_avg_ms": kernel_ms, "launches_per_step": tm["launches"],
             "flops_per_launch": flops_per_launch,
         }
@@ -312,11 +318,11 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if dense else "f32",
+        "dtype": ("fp8" if prec_main == "fp8j_fp8s" else "bf16") if dense else "f32",
         "data": "synthetic",
         "config": {
             "workload": workload,
-            "n": N, "replicas": R, "t_f": T_F, "precision": "fp8j_bf16s", "kernel_path": path,
+            "n": N, "replicas": R, "t_f": T_F, "precision": prec_main if dense else "fp8j_bf16s", "kernel_path": path,
             "j_storage": jfmt,
             "parallelism": "single GPU",
         },
@@ -333,7 +339,7 @@ def main() -> int:
         del src, dst
 
     extra = {}
-    if not args.no_extra and dense:
+    if not args.no_extra and args.workload == "g2000":
         # FP64 GPU path on the same workload: the 5x comparator
         with nmfa.Solver(inst.J, inst.h, precision="fp64") as s64:
             walls, tms = timed_anneals(s64, R, T_F, [77], stream)
@@ -356,6 +362,9 @@ def main() -> int:
         with nmfa.Solver(k2.J, k2.h, precision="fp8j_bf16s") as s16:
             w16, _ = timed_anneals(s16, R, T_F, [3003], stream)
             Ek = s16.energies()[0]
+        with nmfa.Solver(k2.J, k2.h, precision="fp8j_fp8s") as s8:
+            w8k, _ = timed_anneals(s8, R, T_F, [3004], stream)
+            E8k = s8.energies()[0]
         E_target = float(np.percentile(E_ref, 10))
         p16 = float(np.mean(Ek <= E_target))
         p64 = float(np.mean(E64 <= E_target))
@@ -368,6 +377,23 @@ def main() -> int:
             "mean_E_fp8j_bf16s": float(Ek.mean()), "mean_E_fp64": float(E64.mean()),
         }
         extra["g2000_cut_best_headline"] = float((np.triu(inst.J, 1).sum() - E16.min()) / 2)
+        # FP8 spin operands (precision fp8j_fp8s) on the headline workload, and their quality on
+        # the K2000 class at the same target
+        with nmfa.Solver(inst.J, inst.h, precision="fp8j_fp8s") as s8:
+            w8, t8 = timed_anneals(s8, R, T_F, [91, 92], stream)
+            path8 = s8.info()["path"]
+        k8 = min(tm["anneal_ms"] for tm in t8)
+        p8 = float(np.mean(E8k <= E_target))
+        se8 = math.sqrt(p8 * (1 - p8) / R + p64 * (1 - p64) / R)
+        ach8 = flops_per_iter * T_F / (k8 * 1e-3) / 1e12
+        extra["g2000_fp8_spins"] = {
+            "precision": "fp8j_fp8s", "kernel_path": path8, "ms_per_anneal": float(min(w8)),
+            "spin_updates_per_s": spin_updates / (min(w8) * 1e-3), "kernel_ms": k8,
+            "achieved_tflops": ach8, "frac_of_fp8_peak": ach8 / PEAK_FP8_TFLOPS,
+            "frac_of_bf16_peak": ach8 / PEAK_BF16_TFLOPS,
+            "k2000_p_fp8s": p8, "k2000_p_fp64": p64, "k2000_z_vs_fp64": (p8 - p64) / se8 if se8 > 0 else 0.0,
+            "k2000_mean_E_fp8s": float(E8k.mean()),
+        }
         # N = 100 workloads: dense SK (BF16, R=16384) and dense MAX-CUT (the paper's timing case)
         sk = instances.sk(100, 1)
         with nmfa.Solver(sk.J, sk.h, precision="bf16") as sb, nmfa.Solver(sk.J, sk.h, precision="fp64") as sd:

@@ -57,13 +57,19 @@ extern "C" {
  *                 FP32 master state (S is a BF16 copy of the FP32 state).
  * NMFA_FP8J_BF16S J stored as FP8 E4M3 (exact for integers |J| <= 16), widened to BF16 for the
  *                 MFMA; spins as in NMFA_BF16.
+ * NMFA_FP8J_FP8S  J rounded to FP8 E4M3 as for NMFA_FP8J_BF16S and the spin operands rounded to
+ *                 FP8 E4M3 (nearest even): the mean field is an FP4 (J) x FP8 (spins) matrix
+ *                 product with FP32 accumulation; FP32 epilogue and master state. Only for
+ *                 couplings that FP4 E2M1 holds exactly (e.g. {0, +-1}) and n <= 2048 (the
+ *                 register-J kernel, paths 4/5); nmfa_create fails with NMFA_EINVAL otherwise.
  * J values that the chosen storage type cannot represent are rounded to nearest; the energies
  * are always computed from the exact couplings given to nmfa_create. */
 typedef enum nmfa_precision {
   NMFA_FP64 = 0,
   NMFA_FP32 = 1,
   NMFA_BF16 = 2,
-  NMFA_FP8J_BF16S = 3
+  NMFA_FP8J_BF16S = 3,
+  NMFA_FP8J_FP8S = 4
 } nmfa_precision;
 
 /* ---- flags ------------------------------------------------------------------------------------ */

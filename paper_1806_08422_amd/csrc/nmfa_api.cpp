@@ -256,7 +256,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     return fail(NMFA_EINVAL, "nmfa_create: params.struct_size %u != %zu", p->struct_size, sizeof(nmfa_params));
   if (n < 1 || n > 16384) return fail(NMFA_EINVAL, "nmfa_create: n = %d outside [1, 16384]", n);
   if (!J) return fail(NMFA_EINVAL, "nmfa_create: J is NULL");
-  if (p->precision > NMFA_FP8J_BF16S) return fail(NMFA_EINVAL, "nmfa_create: unknown precision %u", p->precision);
+  if (p->precision > NMFA_FP8J_FP8S) return fail(NMFA_EINVAL, "nmfa_create: unknown precision %u", p->precision);
   if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return fail(NMFA_EINVAL, "nmfa_create: alpha must be in (0, 1]");
   if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return fail(NMFA_EINVAL, "nmfa_create: sigma must be >= 0");
   if (p->record_iters < 0) return fail(NMFA_EINVAL, "nmfa_create: record_iters < 0");
@@ -294,7 +294,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   // one pass over the rows (on host threads) gathers what the checks and the set-up need:
   // finiteness, integrality and magnitude, the exact storage formats, nonzeros per row, and
   // h_i^2 + sum_j J_ij^2 summed in column order
-  const bool fp8j = p->precision == NMFA_FP8J_BF16S;
+  const bool fp8j = p->precision == NMFA_FP8J_BF16S || p->precision == NMFA_FP8J_FP8S;
   struct RowInfo {
     int bad_j = -1, sym_j = -1, deg = 0, jmax = 0;
     bool integral = true, fp8x = true, fp4x = true;
@@ -380,7 +380,8 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
 
   // kernel path and padded layout
   const size_t es = c->op_size();
-  const bool bf = (c->prec == NMFA_BF16 || c->prec == NMFA_FP8J_BF16S);
+  const bool fp8s = c->prec == NMFA_FP8J_FP8S;
+  const bool bf = (c->prec == NMFA_BF16 || c->prec == NMFA_FP8J_BF16S || fp8s);
   // exact formats of the couplings the MFMA consumes (FP8-rounded for the FP8-J precision)
   bool j_fp8_exact = true, j_fp4_exact = true;
   for (int i = 0; i < n; ++i) {
@@ -415,12 +416,22 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   // kernel, which reads J from global memory every iteration, is slower than the XCD kernel
   const bool sp_rq = sp_ok && sparse_rq_applies(sp_prec, n, std::max(deg_max, 1));
   const bool sp_auto = sp_ok && n > 256 && 8 * std::max(deg_max, 1) <= n && (sp_rq || !x_ok);
-  if (p->flags & NMFA_FLAG_FORCE_STEP) {
+  if (fp8s) {
+    // FP8 spins run on the register-J kernel only
+    if (!x_rj || (p->flags & (NMFA_FLAG_FORCE_STEP | NMFA_FLAG_FORCE_SPARSE))) {
+      nmfa_destroy(c);
+      return fail(NMFA_EINVAL, "nmfa_create: FP8 spins need the register-J kernel: couplings exact in FP4 E2M1 "
+                               "(e.g. {0, +-1}), n <= 2048, and none of FORCE_STEP / FORCE_SPARSE / FORCE_LDS_J");
+    }
+    c->path = 2;
+  } else if (p->flags & NMFA_FLAG_FORCE_STEP) {
     c->path = 1;
   } else if (p->flags & NMFA_FLAG_FORCE_SPARSE) {
-    if (!sp_ok)
+    if (!sp_ok) {
+      nmfa_destroy(c);
       return fail(NMFA_EINVAL, "nmfa_create: the sparse kernel needs at most 64 couplings per row and a state "
                                "that fits in LDS (n = %d, maximum degree %d)", n, deg_max);
+    }
     c->path = 3;
   } else if ((p->flags & NMFA_FLAG_FORCE_XCD) && x_ok) {
     c->path = 2;
@@ -447,7 +458,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->ell_D = std::max(deg_max, 1);
     c->sp_RB = sp_rb;
   } else if (c->path == 2 && x_rj) {
-    c->xvar = 1;
+    c->xvar = fp8s ? 2 : 1;
     c->Mp = (int)round_up(n, xrj_rows());
     c->Kp = xrj_kp(n);
     c->lds_stride = 0;
@@ -490,7 +501,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   for (int i = lo; i < hi; ++i) {
     for (int j = 0; j < n; ++j) {
       double v = Jf[(size_t)i * n + j];
-      if (c->prec == NMFA_FP8J_BF16S) v = codes.fp8_value(v);
+      if (c->prec == NMFA_FP8J_BF16S || fp8s) v = codes.fp8_value(v);
       const size_t idx = (size_t)i * Kp + j;
       if (j8_small || jfmt2 == 1) {
         jbuf[idx] = codes.fp8(v);
@@ -786,7 +797,8 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
       x.group_base = gb;
       x.force_fenced = (c->flags & NMFA_FLAG_FORCE_FENCED) ? 1 : 0;
       x.nbuf = c->nbuf;
-      if (c->xvar) HIP_TRY(launch_anneal_xrj(a, x, ng, st));
+      if (c->xvar == 2) HIP_TRY(launch_anneal_xrj8(a, x, ng, st));
+      else if (c->xvar) HIP_TRY(launch_anneal_xrj(a, x, ng, st));
       else HIP_TRY(launch_anneal_xcd(c->jfmt, a, x, ng, st));
       ++c->launches;
     }

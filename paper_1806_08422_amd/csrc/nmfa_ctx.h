@@ -71,7 +71,7 @@ struct nmfa_ctx {
   bool timed = false;
 
   size_t acc_size() const { return prec == NMFA_FP64 ? 8 : 4; }
-  size_t op_size() const { return prec == NMFA_FP64 ? 8 : (prec == NMFA_FP32 ? 4 : 2); }
+  size_t op_size() const { return prec == NMFA_FP64 ? 8 : (prec == NMFA_FP32 ? 4 : (prec == NMFA_FP8J_FP8S ? 1 : 2)); }
 };
 
 // Validate one anneal call, make its buffers and fill the kernel arguments (no launch).

@@ -31,7 +31,7 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-enum : int { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2, PREC_FP8J_BF16S = 3 };
+enum : int { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2, PREC_FP8J_BF16S = 3, PREC_FP8J_FP8S = 4 };
 
 // ------------------------------------------------------------------------------------------
 // Philox4x32-10. Counter (q, r, t, 0), key (seed_lo, seed_hi). Each round multiplies words 0

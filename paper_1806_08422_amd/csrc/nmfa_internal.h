@@ -45,6 +45,8 @@ hipError_t launch_anneal_small_batched(int prec, const AnnealArgs* jobs, const i
 hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
 // Register-resident-J variant (FP4 J): 128 rows per workgroup, groups of 64 replicas, Kp = xrj_kp(n).
 hipError_t launch_anneal_xrj(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
+// The same decomposition with FP8 E4M3 spin operands (FP4 x FP8 scaled MFMA); S holds bytes.
+hipError_t launch_anneal_xrj8(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
 int xrj_rows();
 int xrj_group_replicas();
 int xrj_kp(int n);

@@ -344,6 +344,21 @@ __global__ void pack_state_kernel(const acc_t* __restrict__ state, op_t* __restr
   }
 }
 
+// FP8 E4M3 operand copy (the FP8-spin precision), rounded as the annealing kernel's epilogue
+// rounds (v_cvt_pk_fp8_f32: nearest even, saturating), so a resumed run continues bit-exactly.
+__global__ void pack_state_fp8_kernel(const float* __restrict__ state, uint8_t* __restrict__ S, int N, int R, int Kp,
+                                      int ld, int Rp, int zero) {
+  const size_t total = (size_t)Rp * Kp;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / Kp);
+    const int i = (int)(idx - (size_t)r * Kp);
+    float v = 0.0f;
+    if (!zero && r < R && i < N) v = state[(size_t)r * N + i];
+    S[(size_t)r * ld + i] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xff);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Readout: s~ = +1 if s >= 0 (including -0.0), else -1.
 // ------------------------------------------------------------------------------------------
@@ -994,6 +1009,10 @@ hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R,
     case PREC_FP32:
       hipLaunchKernelGGL((pack_state_kernel<float, float>), dim3(blocks), dim3(256), 0, st,
                          (const float*)state, (float*)S, N, R, Kp, ld, Rp, zero);
+      break;
+    case PREC_FP8J_FP8S:
+      hipLaunchKernelGGL(pack_state_fp8_kernel, dim3(blocks), dim3(256), 0, st, (const float*)state, (uint8_t*)S, N,
+                         R, Kp, ld, Rp, zero);
       break;
     default:
       hipLaunchKernelGGL((pack_state_kernel<__bf16, float>), dim3(blocks), dim3(256), 0, st,

@@ -336,7 +336,7 @@ extern "C" int nmfa_server_create(const nmfa_server_params* p, nmfa_server** out
   if (!p) p = &dp;
   if (p->struct_size != sizeof(nmfa_server_params))
     return nmfa_fail(NMFA_EINVAL, "nmfa_server_create: params.struct_size mismatch");
-  if (p->precision > NMFA_FP8J_BF16S || p->max_active < 1 || p->chunk_iters < 1 || p->hbm_budget_bytes == 0)
+  if (p->precision > NMFA_FP8J_FP8S || p->max_active < 1 || p->chunk_iters < 1 || p->hbm_budget_bytes == 0)
     return nmfa_fail(NMFA_EINVAL, "nmfa_server_create: invalid parameters");
   nmfa_server* s = new nmfa_server();
   s->p = *p;

@@ -785,6 +785,272 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
   }
 }
 
+// ---- register-resident J, FP8 spins ----------------------------------------------------------
+// The FP8-spin precision on the same decomposition as anneal_xrj (4 waves per CU, 32 rows of J per
+// wave in FP4 registers, groups of 64 replicas): the mean field runs on the mixed-format matrix
+// instruction v_mfma_scale_f32_16x16x128_f8f6f4 with the FP4 couplings as A operand and the FP8
+// E4M3 spins as B operand, both taken as they are stored (unit scales). The two operands lay out
+// k differently (measured on gfx950 with a one-hot probe): lane 16 g + i of the FP4 operand holds
+// row i at k = 32 g .. 32 g + 31 of the 128-k step (nibbles low first), which is how the J
+// registers are laid out, so J needs no widening; lane 16 g + i of the FP8 operand holds column i
+// at k = 16 g .. 16 g + 15 in its first 16 bytes and at k = 64 + 16 g .. 64 + 16 g + 15 in its
+// last 16. One 128-k chunk is one MFMA per (row tile, column tile). Spin chunks are 64 replicas x
+// 128 bytes (8 KB); unit u (16 k) of replica q is stored at u ^ ((q >> 1) & 7) of its 128-byte
+// row, so that the 16 lanes a ds_read_b128 serves hit 16 distinct 16-byte bank groups. The
+// epilogue packs each lane's four new spins of a column tile into one 32-bit word.
+constexpr int XRJ8_CHB = XRJ_RG * XRJ_KC;  // bytes of one chunk: 64 replicas x 128 k, FP8
+
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+template <int NCH>
+__global__ __launch_bounds__(256, 1) void anneal_xrj8(AnnealArgs a, XcdArgs x) {
+  extern __shared__ __align__(16) unsigned char smem[];  // XRJ_NB chunk buffers
+  __shared__ unsigned abort_word;                        // the group barrier's decision
+  constexpr int NB = XRJ_NB;
+  constexpr int RT = 2;
+  constexpr int DPW = 2;  // 1 KB direct-to-LDS loads per wave and chunk (8 KB over 4 waves)
+  static_assert(DPW * (XRJ_LA - 1) <= 63, "wait counts fit the vmcnt field");
+  static_assert(XRJ_LA <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
+  const int N = a.N, ks = x.ks;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g4 = lane >> 4, c = lane & 15;
+
+  const XcdSlot slot = xcd_register(x, tid);
+  const unsigned my_group = slot.my_group;
+  const int group = (int)my_group + x.group_base;
+  const int rb = slot.rb;
+  const bool xcd_mode = slot.xcd_mode;
+  bool aborted = slot.aborted;
+
+  // J of this wave, as in anneal_xrj: jr[ch][q][rt] = the 8 FP4 couplings of row
+  // rb*128 + 32*wave + 16*rt + c at k = 128*ch + 32*g4 + 8*q .. +7
+  uint32_t jr[NCH][4][RT];
+  {
+    const int jrow = 64 * NCH;  // bytes of one FP4 row (Kp / 2)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const unsigned char* p = reinterpret_cast<const unsigned char*>(a.J) +
+                               (size_t)(rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + c) * jrow + 16 * g4;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const uint4 v = *reinterpret_cast<const uint4*>(p + 64 * ch);
+        jr[ch][0][rt] = v.x;
+        jr[ch][1][rt] = v.y;
+        jr[ch][2][rt] = v.z;
+        jr[ch][3][rt] = v.w;
+      }
+    }
+  }
+
+  const float* inv_g = reinterpret_cast<const float*>(a.inv_norm);
+  const float* h_g = reinterpret_cast<const float*>(a.hterm);
+  float* state = reinterpret_cast<float*>(a.state);
+  float* traj = reinterpret_cast<float*>(a.traj);
+  const float* coef = reinterpret_cast<const float*>(a.coef);
+  float inv[RT][4], hv[RT][4], s[RT][4][4];
+  int row0[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    row0[rt] = rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + 4 * g4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      inv[rt][v] = inv_g[row0[rt] + v];
+      hv[rt][v] = h_g[row0[rt] + v];
+    }
+  }
+  const int rgroup0 = group * XRJ_RG;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int r = rgroup0 + 16 * ct + c;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0[rt] + v;
+        s[rt][ct][v] = (a.load_state && r < a.R && i < N) ? state[(size_t)r * N + i] : 0.0f;
+      }
+  }
+  const float sg = (float)a.sigma;
+  const float neg2ln2_s2 = -2.0f * 0.6931471805599453f * sg * sg;
+  const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha);
+  float zn[RT][4][4];
+  auto draw_noise_half = [&](int tt, int ct0) {
+#pragma unroll
+    for (int ct = ct0; ct < ct0 + 2; ++ct)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        sigma_gauss4_f32(philox4x32_10((uint32_t)(row0[rt] >> 2), (uint32_t)(rgroup0 + 16 * ct + c), (uint32_t)tt, 0u,
+                                       a.key0, a.key1),
+                         neg2ln2_s2, zn[rt][ct]);
+  };
+  auto pin_noise_half = [&](int ct0) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = ct0; ct < ct0 + 2; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(zn[rt][ct][v]));
+  };
+  draw_noise_half(a.t_begin, 0);
+  draw_noise_half(a.t_begin, 2);
+
+  // spin fragments: lane (c, g4) of column tile ct reads units g4 and g4 + 4 of replica 16*ct + c
+  // (the FP8 operand's k layout); (q >> 1) & 7 does not depend on ct, and the column tiles are
+  // 2 KB apart
+  int boff[2];
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) boff[hf] = c * 128 + ((g4 + 4 * hf) ^ ((c >> 1) & 7)) * 16;
+  // direct-to-LDS loads: block b (1 KB) holds replicas 8b .. 8b + 7; lane l fills position l % 8
+  // of replica 8b + l / 8 with the global unit that the swizzle puts there
+  unsigned dma_off[DPW];
+#pragma unroll
+  for (int u = 0; u < DPW; ++u) {
+    const int blk = DPW * wave + u;
+    const int q = 8 * blk + (lane >> 3);
+    const int pos = lane & 7;
+    dma_off[u] = (unsigned)(q * ks + (pos ^ ((q >> 1) & 7)) * 16);  // bytes within the group's block
+  }
+
+  const unsigned char* S0 = reinterpret_cast<const unsigned char*>(x.S[0]);
+  const unsigned char* S1 = reinterpret_cast<const unsigned char*>(x.S[1]);
+  unsigned char* ring = smem;
+  unsigned* bar = &x.ctl[CTL_BAR + 16 * (int)my_group];
+  int epoch = 0;
+  __syncthreads();
+
+  for (int t = a.t_begin; t <= a.t_end && !aborted; ++t) {
+    const unsigned char* Sg = ((t & 1) ? S1 : S0) + (size_t)group * XRJ_RG * ks;
+    unsigned char* Snext = const_cast<unsigned char*>((t & 1) ? S0 : S1);
+
+    auto issue = [&](int ch, int buf) {
+#pragma unroll
+      for (int u = 0; u < DPW; ++u)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(Sg + dma_off[u] + ch * XRJ_KC),
+                                         ring + buf * XRJ8_CHB + (DPW * wave + u) * 1024, 16, 0, 0);
+    };
+    i32x8 fb[2][4];  // [register set][column tile]: the spins of one 128-k chunk
+    auto load = [&](int ch) {
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const unsigned char* base = smem + (ch % NB) * XRJ8_CHB + 2048 * ct;
+        const uint4 lo = *reinterpret_cast<const uint4*>(base + boff[0]);
+        const uint4 hi = *reinterpret_cast<const uint4*>(base + boff[1]);
+        fb[ch & 1][ct] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      }
+    };
+    f32x4 acc[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
+
+    constexpr int PRO = XRJ_LA < NCH ? XRJ_LA : NCH;
+#pragma unroll
+    for (int q = 0; q < PRO; ++q) issue(q, q);
+    wait_vm<DPW * (PRO - 1)>();
+    bare_barrier();
+    load(0);
+    // chunk ch: chunk ch+1 has landed for every wave once they meet at the barrier (and every
+    // wave is done with chunk ch-1); its spins are read into the other register set while the
+    // MFMAs of chunk ch run; chunk ch+XRJ_LA goes to buffer (ch+XRJ_LA) % NB, last used by chunk
+    // ch+XRJ_LA-NB <= ch-1
+    static_for(
+        [&](auto chc) {
+          constexpr int ch = decltype(chc)::value;
+          if constexpr (ch + 1 < NCH) {
+            constexpr int last_issued = (ch + XRJ_LA - 1 < NCH - 1) ? ch + XRJ_LA - 1 : NCH - 1;
+            wait_vm<DPW * (last_issued - (ch + 1))>();
+            __builtin_amdgcn_sched_barrier(0);
+            bare_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (ch + XRJ_LA < NCH) issue(ch + XRJ_LA, (ch + XRJ_LA) % NB);
+          }
+          wait_lds();
+          if constexpr (ch + 1 < NCH) load(ch + 1);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+            const i32x8 af = i32x8{(int)jr[ch][0][rt], (int)jr[ch][1][rt], (int)jr[ch][2][rt], (int)jr[ch][3][rt],
+                                   0, 0, 0, 0};
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+              acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af, fb[ch & 1][ct], acc[rt][ct], 4, 0, 0,
+                                                                              0x7f7f7f7f, 0, 0x7f7f7f7f);
+          }
+          // The MFMA builtin has no side effects, so without this the compiler sinks every chunk's
+          // MFMAs to the epilogue and keeps all chunks' spin fragments live: an empty volatile
+          // statement that takes the accumulators (in the accumulation registers) holds each
+          // chunk's MFMAs in its own step.
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) asm volatile("" : "+a"(acc[rt][ct]));
+          __builtin_amdgcn_sched_barrier(0);
+        },
+        std::make_integer_sequence<int, NCH>{});
+
+    // ---- fused epilogue --------------------------------------------------------------------
+    const float coef_t = coef[t - 1];
+    const int k_rec = t - a.t_begin;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int r = rgroup0 + 16 * ct + c;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float xf = fmaf(acc[rt][ct][v], inv[rt][v], hv[rt][v]);
+          const float phi = a.negate_noise ? xf - zn[rt][ct][v] : xf + zn[rt][ct][v];
+          const float sh = neg_tanh_from_exp2_arg(phi * coef_t);
+          float sv = fmaf(alpha, sh, oma * s[rt][ct][v]);
+          if (row0[rt] + v >= N) sv = 0.0f;
+          s[rt][ct][v] = sv;
+        }
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(s[rt][ct][0], s[rt][ct][1], 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(s[rt][ct][2], s[rt][ct][3], w, true);
+        *reinterpret_cast<int*>(Snext + (size_t)r * ks + row0[rt]) = w;
+        if (traj && k_rec < a.record && r < a.R) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (row0[rt] + v < N) traj[((size_t)k_rec * a.R + r) * N + row0[rt] + v] = s[rt][ct][v];
+        }
+      }
+    }
+
+    if (t < a.t_end) {
+      xcd_group_arrive(bar, xcd_mode, tid);
+      draw_noise_half(t + 1, 0);
+      pin_noise_half(0);
+      unsigned seen = 0;
+      __builtin_amdgcn_sched_barrier(0);
+      if (tid == 0) seen = ld_dev(bar);
+      __builtin_amdgcn_sched_barrier(0);
+      draw_noise_half(t + 1, 2);
+      pin_noise_half(2);
+      aborted = xrj_group_wait(x, bar, (unsigned)++epoch, xcd_mode, tid, seen, &abort_word);
+    }
+  }
+
+  // ---- final state and readout ---------------------------------------------------------------
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int r = rgroup0 + 16 * ct + c;
+    if (r >= a.R) continue;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0[rt] + v;
+        if (i < N) {
+          state[(size_t)r * N + i] = s[rt][ct][v];
+          if (a.spins) a.spins[(size_t)r * N + i] = (s[rt][ct][v] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
+        }
+      }
+  }
+}
+
 size_t xcd_j_lds_bytes(int jfmt, int Kp) {
   return (size_t)XCD_ROWS * (jfmt == 0 ? (size_t)Kp * 2 : (jfmt == 1 ? (size_t)Kp : (size_t)Kp / 2));
 }
@@ -859,6 +1125,25 @@ static hipError_t launch_resident(const void* fn, int grid, int block, size_t ld
   XcdArgs xx = x;
   void* args[] = {&aa, &xx};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, st);
+}
+
+static const void* xrj8_fn(int Kp) {
+  switch (Kp) {
+    case 512: return (const void*)anneal_xrj8<4>;
+    case 768: return (const void*)anneal_xrj8<6>;
+    case 1024: return (const void*)anneal_xrj8<8>;
+    case 1280: return (const void*)anneal_xrj8<10>;
+    case 1536: return (const void*)anneal_xrj8<12>;
+    case 1792: return (const void*)anneal_xrj8<14>;
+    case 2048: return (const void*)anneal_xrj8<16>;
+    default: return nullptr;
+  }
+}
+
+hipError_t launch_anneal_xrj8(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
+  const void* fn = xrj8_fn(a.Kp);
+  if (!fn) return hipErrorInvalidValue;
+  return launch_resident(fn, groups * x.P, 256, (size_t)XRJ_NB * XRJ8_CHB, a, x, st);
 }
 
 hipError_t launch_anneal_xrj(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {

@@ -24,8 +24,8 @@ NMFA_EDEVICE = -3
 NMFA_ESTATE = -4
 NMFA_ECANCELED = -5
 
-FP64, FP32, BF16, FP8J_BF16S = 0, 1, 2, 3
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp8j_bf16s": FP8J_BF16S}
+FP64, FP32, BF16, FP8J_BF16S, FP8J_FP8S = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp8j_bf16s": FP8J_BF16S, "fp8j_fp8s": FP8J_FP8S}
 
 FLAG_NEGATE_NOISE = 0x1
 FLAG_UPPER_TRIANGULAR = 0x2
