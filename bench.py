@@ -218,10 +218,11 @@ def serving_leg(nmfa, instances_mod, n_burst: int, n_stream: int, budget_bytes: 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("g2000", "d3_2000", "g2000_fp8s"), default="g2000",
+    ap.add_argument("--workload", choices=("g2000", "d3_2000", "g2000_fp8s", "sk8192"), default="g2000",
                     help="g2000: dense G(2000, 0.5) MAX-CUT (default); d3_2000: random 3-regular "
                          "MAX-CUT at N = 2000 on the sparse kernel; g2000_fp8s: the default workload "
-                         "with FP8 spin operands (precision fp8j_fp8s)")
+                         "with FP8 spin operands (precision fp8j_fp8s); sk8192: dense SK at N = 8192, "
+                         "R = 1024, t_f = 200 on the tiled per-iteration kernel (BF16)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -249,9 +250,15 @@ def main() -> int:
     stream = torch.cuda.current_stream().cuda_stream
 
     N, R, T_F = 2000, 1024, 5000
-    dense = args.workload in ("g2000", "g2000_fp8s")
-    prec_main = "fp8j_fp8s" if args.workload == "g2000_fp8s" else "fp8j_bf16s"
-    inst = instances.gnp(N, 0.5, 1) if dense else instances.random_regular(N, 3, 1)
+    big = args.workload == "sk8192"
+    if big:
+        N, T_F = 8192, 200
+    dense = args.workload in ("g2000", "g2000_fp8s", "sk8192")
+    prec_main = {"g2000_fp8s": "fp8j_fp8s", "sk8192": "bf16"}.get(args.workload, "fp8j_bf16s")
+    if big:
+        inst = instances.sk(N, 1)
+    else:
+        inst = instances.gnp(N, 0.5, 1) if dense else instances.random_regular(N, 3, 1)
     spin_updates = N * R * T_F
     flops_per_iter = 2.0 * N * N * R  # algorithmic: 2N flops per spin update (dense J)
 
@@ -287,9 +294,12 @@ def main() -> int:
         workload = ("dense random-graph MAX-CUT G(2000,0.5), J in {0,1}, h=0, R=1024, t_f=5000, "
                     "J rounded to FP8-E4M3 (exact here) / spins " + ("FP8-E4M3" if fp8s else "BF16") +
                     " / FP32 accumulate")
+        if big:
+            workload = ("dense SK N=8192, J in {-1,+1}, h=0, R=1024, t_f=200, J and spins BF16 / FP32 "
+                        "accumulate, tiled per-iteration kernel")
         roofline = {
             "bound": "mfma", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved_tflops / peak, "traffic": None if fp8s else measured_traffic(path),
+            "frac": achieved_tflops / peak, "traffic": None if (fp8s or big) else measured_traffic(path),
             "kernel_avg_ms": kernel_ms, "launches_per_step": tm["launches"],
             "flops_per_launch": flops_per_launch,
         }
@@ -451,6 +461,19 @@ def main() -> int:
             p20 = float(np.mean(s64.energies()[0] <= e0_sk))
         extra["sk20_fp64"] = {"R": 256, "t_f": 1000, "ms_per_anneal": w20[0], "E_ground": e0_sk, "p_fp64": p20,
                               "tts99_s": tts99(w20[0] * 1e-3 / 256, p20)}
+        # dense SK at N = 8192 (beyond the persistent kernels): the tiled per-iteration kernel
+        sk8 = instances.sk(8192, 1)
+        with nmfa.Solver(sk8.J, sk8.h, precision="bf16") as sb8:
+            wb8, tb8 = timed_anneals(sb8, 1024, 200, [71, 72], stream)
+            path_b8 = sb8.info()["path"]
+        kb8 = min(tm["anneal_ms"] for tm in tb8)
+        fl8 = 2.0 * 8192 * 8192 * 1024 * 200
+        extra["sk8192_bf16_step"] = {
+            "R": 1024, "t_f": 200, "kernel_path": path_b8, "ms_per_anneal": float(min(wb8)),
+            "spin_updates_per_s": 8192 * 1024 * 200 / (min(wb8) * 1e-3), "kernel_ms": kb8,
+            "achieved_tflops": fl8 / (kb8 * 1e-3) / 1e12, "frac_of_bf16_peak": fl8 / (kb8 * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+        }
+        del sk8
         mc = instances.gnp(100, 0.5, 1)
         with nmfa.Solver(mc.J, mc.h, precision="bf16") as sm:
             wm, _ = timed_anneals(sm, 10000, 1000, [31, 32, 33], stream)

@@ -470,7 +470,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->jfmt = x_jfmt;
     c->nbuf = x_nbuf;
   } else {
-    c->Mp = (int)round_up(n, 64);
+    c->Mp = (int)round_up(n, 128);  // the tiled per-iteration kernel works on 128-row tiles
     c->Kp = c->Mp;
     c->lds_stride = 0;
   }

@@ -847,8 +847,160 @@ size_t small_lds_bytes(int prec, int Mp, int stride) {
   return ((size_t)Mp + 32) * stride * es;
 }
 
+// ------------------------------------------------------------------------------------------
+// anneal_step_tiled: one iteration for large N with BF16 operands (BF16 and FP8-J precisions),
+// as a tiled matrix product with the fused epilogue. Workgroup (bx, by) owns rows
+// [128 bx, +128) x replicas [128 by, +128); wave w owns rows 64 (w / 2) .. +63 and replicas
+// 64 (w % 2) .. +63 (4 x 4 MFMA tiles of 16 x 16). J [Mp][Kp] and S_cur [Rp][Kp] (both k
+// contiguous) stream through a 3-stage LDS ring of 64-k blocks filled by direct-to-LDS loads
+// (32 KB per stage: 128 rows of J and 128 replicas of S, 128 bytes each); unit u (8 k) of tile row
+// q sits at u ^ ((q >> 1) & 7) of its row, so the 16 lanes a ds_read_b128 serves hit distinct
+// bank groups. Needs Mp % 128 == 0, S buffers of roundup(R, 128) rows (padding rows zero).
+// ------------------------------------------------------------------------------------------
+constexpr int ST_M = 128;                 // rows per workgroup
+constexpr int ST_R = 128;                 // replicas per workgroup
+constexpr int ST_K = 64;                  // k per block
+constexpr int ST_TILE = ST_M * ST_K * 2;  // bytes of one operand tile (16 KB)
+constexpr int ST_STAGES = 3;
+
+template <int NV>
+__device__ __forceinline__ void step_wait_vm() {
+  static_assert(NV >= 0 && NV <= 63, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt(0xF70 | (NV & 15) | ((NV >> 4) << 14));
+}
+
+__global__ __launch_bounds__(256, 1) void anneal_step_tiled(AnnealArgs a, const __bf16* __restrict__ S_cur,
+                                                            __bf16* __restrict__ S_next, int t) {
+  extern __shared__ __align__(16) unsigned char smem_st[];  // ST_STAGES x (J tile, S tile)
+  const int N = a.N, Kp = a.Kp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g4 = lane >> 4, c = lane & 15;
+  const int m0 = blockIdx.x * ST_M, r0 = blockIdx.y * ST_R;
+  const int wm = 64 * (wave >> 1), wr = 64 * (wave & 1);
+
+  // direct-to-LDS loads: 32 blocks of 1 KB per stage, wave w issues blocks 8w .. 8w + 7 (waves 0
+  // and 1 the J tile, waves 2 and 3 the S tile); block b holds tile rows 8 (b % 16) .. +7 and lane
+  // l fills position l % 8 of row 8 (b % 16) + l / 8 with the global unit the swizzle puts there
+  const unsigned char* src = reinterpret_cast<const unsigned char*>(wave < 2 ? a.J : (const void*)S_cur);
+  const int row_base = wave < 2 ? m0 : r0;
+  size_t goff[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int b = 8 * wave + u;
+    const int q = 8 * (b & 15) + (lane >> 3);
+    const int unit = (lane & 7) ^ ((q >> 1) & 7);
+    goff[u] = (size_t)(row_base + q) * Kp * 2 + unit * 16;
+  }
+  unsigned char* ring = smem_st;
+  const int dst_half = wave < 2 ? 0 : ST_TILE;
+  auto issue = [&](int kb, int stage) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(src + goff[u] + (size_t)kb * ST_K * 2),
+                                       ring + stage * 2 * ST_TILE + dst_half + ((8 * wave + u) & 15) * 1024, 16, 0, 0);
+  };
+  // fragment offsets within a tile: lane (c, g4) reads unit 4 s + g4 of row (16 t + c) at k step s
+  int foff[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) foff[s] = c * 128 + (((4 * s + g4) ^ ((c >> 1) & 7)) * 16);
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
+
+  const int nkb = Kp / ST_K;
+  issue(0, 0);
+  if (nkb > 1) issue(1, 1);
+  for (int kb = 0; kb < nkb; ++kb) {
+    // this wave's part of block kb has landed (block kb + 1 may still be in flight)
+    if (kb + 1 < nkb) step_wait_vm<8>();
+    else step_wait_vm<0>();
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();  // every wave's part landed; every wave is done with block kb - 1
+    __builtin_amdgcn_sched_barrier(0);
+    if (kb + 2 < nkb) issue(kb + 2, (kb + 2) % ST_STAGES);
+    const unsigned char* At = ring + (kb % ST_STAGES) * 2 * ST_TILE + wm * 128;
+    const unsigned char* Bt = ring + (kb % ST_STAGES) * 2 * ST_TILE + ST_TILE + wr * 128;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 af[4], bfr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        af[i] = *reinterpret_cast<const bf16x8*>(At + 2048 * i + foff[s]);
+        bfr[i] = *reinterpret_cast<const bf16x8*>(Bt + 2048 * i + foff[s]);
+      }
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rt], bfr[ct], acc[rt][ct], 0, 0, 0);
+    }
+    // the reads of this block are complete before the next barrier frees its buffer
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // ---- fused epilogue (the FP32 epilogue shared by every kernel) --------------------------------
+  const float* inv_g = reinterpret_cast<const float*>(a.inv_norm);
+  const float* h_g = reinterpret_cast<const float*>(a.hterm);
+  float* state = reinterpret_cast<float*>(a.state);
+  float* traj = reinterpret_cast<float*>(a.traj);
+  const float coef_t = reinterpret_cast<const float*>(a.coef)[t - 1];
+  const int k_rec = t - a.t_begin;
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) {
+    const int row0 = m0 + wm + 16 * rt + 4 * g4;
+    float inv[4], hv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      inv[v] = inv_g[row0 + v];
+      hv[v] = h_g[row0 + v];
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int r = r0 + wr + 16 * ct + c;
+      const bool live_r = r < a.R;
+      float sv[4], fld[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        fld[v] = acc[rt][ct][v];
+        sv[v] = (live_r && row0 + v < N) ? state[(size_t)r * N + row0 + v] : 0.0f;
+      }
+      Epilogue<PREC_BF16>::apply(fld, inv, hv, sv, a, coef_t, (uint32_t)(row0 >> 2), (uint32_t)r, (uint32_t)t);
+      __bf16 outv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (row0 + v >= N || !live_r) sv[v] = 0.0f;
+        outv[v] = (__bf16)sv[v];
+      }
+      *reinterpret_cast<uint2*>(S_next + (size_t)r * Kp + row0) = *reinterpret_cast<const uint2*>(outv);
+      if (live_r) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (row0 + v < N) {
+            state[(size_t)r * N + row0 + v] = sv[v];
+            if (traj && k_rec < a.record) traj[((size_t)k_rec * a.R + r) * N + row0 + v] = sv[v];
+          }
+      }
+    }
+  }
+}
+
 hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
                               hipStream_t st) {
+  if ((prec == PREC_BF16 || prec == PREC_FP8J_BF16S) && a.Mp % ST_M == 0 && a.Kp % ST_K == 0) {
+    const size_t lds = (size_t)ST_STAGES * 2 * ST_TILE;
+    hipError_t e = hipFuncSetAttribute((const void*)anneal_step_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid(a.Mp / ST_M, (a.R + ST_R - 1) / ST_R);
+    hipLaunchKernelGGL(anneal_step_tiled, grid, dim3(256), lds, st, a, (const __bf16*)S_cur, (__bf16*)S_next, t);
+    return hipGetLastError();
+  }
   const dim3 grid(a.Mp / 64, a.Rp / 64);
   switch (prec) {
     case PREC_FP64:
