@@ -861,7 +861,7 @@ constexpr int ST_M = 128;                 // rows per workgroup
 constexpr int ST_R = 128;                 // replicas per workgroup
 constexpr int ST_K = 64;                  // k per block
 constexpr int ST_TILE = ST_M * ST_K * 2;  // bytes of one operand tile (16 KB)
-constexpr int ST_STAGES = 3;
+constexpr int ST_STAGES = 4;
 
 template <int NV>
 __device__ __forceinline__ void step_wait_vm() {
@@ -915,30 +915,35 @@ __global__ __launch_bounds__(256, 1) void anneal_step_tiled(AnnealArgs a, const 
   const int nkb = Kp / ST_K;
   issue(0, 0);
   if (nkb > 1) issue(1, 1);
+  if (nkb > 2) issue(2, 2);
   for (int kb = 0; kb < nkb; ++kb) {
-    // this wave's part of block kb has landed (block kb + 1 may still be in flight)
-    if (kb + 1 < nkb) step_wait_vm<8>();
+    // this wave's part of block kb has landed (blocks kb + 1, kb + 2 may still be in flight)
+    if (kb + 2 < nkb) step_wait_vm<16>();
+    else if (kb + 1 < nkb) step_wait_vm<8>();
     else step_wait_vm<0>();
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_barrier();  // every wave's part landed; every wave is done with block kb - 1
     __builtin_amdgcn_sched_barrier(0);
-    if (kb + 2 < nkb) issue(kb + 2, (kb + 2) % ST_STAGES);
+    if (kb + 3 < nkb) issue(kb + 3, (kb + 3) % ST_STAGES);
     const unsigned char* At = ring + (kb % ST_STAGES) * 2 * ST_TILE + wm * 128;
     const unsigned char* Bt = ring + (kb % ST_STAGES) * 2 * ST_TILE + ST_TILE + wr * 128;
+    // both k steps' fragments are read up front, so the second step's reads land under the
+    // first step's MFMAs
+    bf16x8 af[2][4], bfr[2][4];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      bf16x8 af[4], bfr[4];
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        af[i] = *reinterpret_cast<const bf16x8*>(At + 2048 * i + foff[s]);
-        bfr[i] = *reinterpret_cast<const bf16x8*>(Bt + 2048 * i + foff[s]);
+        af[s][i] = *reinterpret_cast<const bf16x8*>(At + 2048 * i + foff[s]);
+        bfr[s][i] = *reinterpret_cast<const bf16x8*>(Bt + 2048 * i + foff[s]);
       }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rt], bfr[ct], acc[rt][ct], 0, 0, 0);
-    }
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s][rt], bfr[s][ct], acc[rt][ct], 0, 0, 0);
     // the reads of this block are complete before the next barrier frees its buffer
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_sched_barrier(0);
