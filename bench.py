@@ -402,7 +402,7 @@ def main() -> int:
             "achieved_tflops": ach8, "frac_of_fp8_peak": ach8 / PEAK_FP8_TFLOPS,
             "frac_of_bf16_peak": ach8 / PEAK_BF16_TFLOPS,
             "k2000_p_fp8s": p8, "k2000_p_fp64": p64, "k2000_z_vs_fp64": (p8 - p64) / se8 if se8 > 0 else 0.0,
-            "k2000_mean_E_fp8s": float(E8k.mean()),
+            "k2000_mean_E_fp8s": float(E8k.mean()), "k2000_tts99_s_fp8s": tts99(w8k[0] * 1e-3 / R, p8),
         }
         # N = 100 workloads: dense SK (BF16, R=16384) and dense MAX-CUT (the paper's timing case)
         sk = instances.sk(100, 1)
