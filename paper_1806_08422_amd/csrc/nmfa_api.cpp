@@ -754,8 +754,16 @@ extern "C" int nmfa_anneal_range(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_
   return ctx_launch_run(c, R, t_f, t_begin, t_end, seed, (hipStream_t)hip_stream, true);
 }
 
+bool ctx_group_shape(const nmfa_ctx* c, int32_t R, int* P, int* G) {
+  if (c->path != 2) return false;
+  const int Rg = c->xvar ? xrj_group_replicas() : xcd_group_replicas();
+  *G = (R + Rg - 1) / Rg;
+  *P = c->Mp / (c->xvar ? xrj_rows() : xcd_rows());
+  return true;
+}
+
 int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end, uint64_t seed,
-                   hipStream_t st, bool finish) {
+                   hipStream_t st, bool finish, int max_workgroups) {
   AnnealArgs a{};
   int rc = ctx_prepare_run(c, R, t_f, t_begin, t_end, seed, st, &a);
   if (rc != NMFA_OK) return rc;
@@ -776,7 +784,9 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     const int P = c->Mp / (c->xvar ? xrj_rows() : xcd_rows());
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-    const int per_launch = std::max(1, std::min(cus, 256) / P);  // the control block serves 256 workgroups
+    int width = std::min(cus, 256);  // the control block serves 256 workgroups
+    if (max_workgroups > 0) width = std::min(width, max_workgroups);
+    const int per_launch = std::max(1, width / P);
     HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[t_begin & 1], c->n, R, c->Kp, c->Ks, G * Rg,
                               t_begin == 1 ? 1 : 0, st));
     HIP_TRY(hipMemsetAsync(c->d_ctl, 0, (size_t)xcd_ctl_words() * 4, st));

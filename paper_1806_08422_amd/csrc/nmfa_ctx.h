@@ -77,9 +77,15 @@ struct nmfa_ctx {
 // Validate one anneal call, make its buffers and fill the kernel arguments (no launch).
 int ctx_prepare_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end, uint64_t seed,
                     hipStream_t st, nmfa::AnnealArgs* out);
+// For the persistent XCD-group path (whose workgroups wait for each other, so that all of one
+// launch must be resident at once): P workgroups per replica group and G groups for R replicas.
+// Returns false for the other paths.
+bool ctx_group_shape(const nmfa_ctx* c, int32_t R, int* P, int* G);
 // Enqueue iterations t_begin..t_end on the context's kernel path; with finish, also the energies.
+// max_workgroups > 0 caps the workgroups of one group-kernel launch (more launches, one after the
+// other on st, cover the remaining groups); results do not depend on it.
 int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end, uint64_t seed,
-                   hipStream_t st, bool finish);
+                   hipStream_t st, bool finish, int max_workgroups = 0);
 // Enqueue the energies of the readout and mark the results valid.
 int ctx_finish_run(nmfa_ctx* c, hipStream_t st);
 // Record an error message for nmfa_last_error() and return code.

@@ -7,11 +7,16 @@
 //     (anneal_small_batched over every request's replica blocks; each workgroup reads its own
 //     request's arguments), so newly admitted work overlaps with running work on the device;
 //   * larger requests advance by the same chunk on their own kernels in the same round, on the
-//     other streams, so that their kernels run side by side with the batched launch and with
-//     each other. Requests on the persistent XCD-group kernels share one stream: the workgroups
-//     of such a launch wait for each other, and two of them side by side could each hold part
-//     of the chip the other needs. The sparse and per-iteration kernels never wait for other
-//     workgroups, so they spread over the remaining streams and at worst delay a group
+//     other three streams, so that their kernels run side by side with the batched launch and
+//     with each other. The workgroups of one persistent XCD-group launch wait for each other, so
+//     group launches run side by side only where all of them fit on the chip at once: each of
+//     the three streams has a workgroup budget (half, a quarter and a quarter of the CUs, in
+//     multiples of the XCD count), each group launch on a stream is capped at that stream's
+//     budget (a request that needs more takes several launches in turn), and a stream runs one
+//     launch at a time, so the resident group workgroups never exceed the CUs. Requests go to the
+//     stream that would finish them first (largest first). A round with a single group request
+//     gives it the whole chip. The sparse and per-iteration kernels never wait for other
+//     workgroups, so they spread over the second and third streams and at worst delay a group
 //     launch's start;
 //   * between rounds the spin state stays on the device (resuming is bit-exact), finished
 //     requests return their energies/spins and release their memory, and queued requests are
@@ -83,7 +88,8 @@ struct nmfa_server {
   nmfa_server_params p{};
   int device = 0;
   hipStream_t stream = nullptr;            // the batched small-N launch
-  hipStream_t lanes[SERVER_LANES] = {};    // [0]: XCD-group kernels; [1..]: sparse, per-iteration
+  hipStream_t lanes[SERVER_LANES] = {};    // group kernels on all three; sparse, per-iteration on [1..]
+  int cus = 256;                           // compute units of the device
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Job*> queue;
@@ -126,6 +132,48 @@ void finish_job(nmfa_server* s, Job* j, int status) {
   else ++s->st.failed;
 }
 
+// Stream and per-launch workgroup cap of each of the round's XCD-group requests (lane -1 for the
+// others). Budgets: lane 0 half of the CUs, lanes 1 and 2 a quarter each, rounded down to a
+// multiple of the 8 XCDs so that the round-robin placement of a launch's workgroups over the XCDs
+// also fits. A request goes to the lane on which, after the work already given to it, it would
+// finish first, with per-launch time taken as proportional to Mp (the k length) and the number
+// of launches as its groups over the groups that fit the budget.
+void plan_group_lanes(const nmfa_server* s, const std::vector<Job*>& jobs, const std::vector<int>& t_end,
+                      std::vector<int>* lane, std::vector<int>* cap) {
+  lane->assign(jobs.size(), -1);
+  cap->assign(jobs.size(), 0);
+  std::vector<int> idx, P(jobs.size()), G(jobs.size());
+  for (size_t k = 0; k < jobs.size(); ++k)
+    if (jobs[k]->ctx && ctx_group_shape(jobs[k]->ctx, jobs[k]->R, &P[k], &G[k])) idx.push_back((int)k);
+  for (int k : idx) (*lane)[k] = 0;  // default: one stream, whole chip
+  const int budget[SERVER_LANES] = {s->cus / 2 / 8 * 8, s->cus / 4 / 8 * 8, s->cus / 4 / 8 * 8};
+  if (idx.size() < 2 || budget[1] < 8) return;
+  for (int k : idx)
+    if (P[k] > budget[0]) return;
+  auto iters = [&](int k) { return (double)(t_end[k] - jobs[k]->t_done); };
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) {
+    return (double)G[x] * P[x] * jobs[x]->ctx->Mp * iters(x) > (double)G[y] * P[y] * jobs[y]->ctx->Mp * iters(y);
+  });
+  double load[SERVER_LANES] = {0, 0, 0};
+  for (int k : idx) {
+    int best = -1;
+    double best_end = 0, best_t = 0;
+    for (int L = 0; L < SERVER_LANES; ++L) {
+      if (P[k] > budget[L]) continue;
+      const int per = budget[L] / P[k];
+      const double t = (double)((G[k] + per - 1) / per) * jobs[k]->ctx->Mp * iters(k);
+      if (best < 0 || load[L] + t < best_end) {
+        best = L;
+        best_end = load[L] + t;
+        best_t = t;
+      }
+    }
+    load[best] += best_t;
+    (*lane)[k] = best;
+    (*cap)[k] = budget[best];
+  }
+}
+
 int ensure_staging(nmfa_server* s, int n_jobs, int n_tasks) {
   if (n_jobs > s->cap_jobs) {
     (void)hipFree(s->d_jobs);
@@ -144,54 +192,64 @@ int ensure_staging(nmfa_server* s, int n_jobs, int n_tasks) {
   return NMFA_OK;
 }
 
+// Admit queued requests (FIFO by device memory budget and slots; the head of the queue is never
+// overtaken) and upload their instances. Runs while the previous round's kernels execute: the
+// server's streams do not synchronise with the null stream that the uploads use.
+void admit_queued(nmfa_server* s) {
+  std::vector<Job*> admitted;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    while (!s->queue.empty() && (int)(s->active.size() + admitted.size()) < s->p.max_active) {
+      Job* j = s->queue.front();
+      if (j->bytes > s->p.hbm_budget_bytes) {
+        s->queue.pop_front();
+        j->msg = "request needs more device memory than the whole budget";
+        j->bytes = 0;  // never charged to the budget
+        finish_job(s, j, NMFA_ENOMEM);
+        s->cv_done.notify_all();
+        continue;
+      }
+      if (s->used_bytes + j->bytes > s->p.hbm_budget_bytes) break;
+      s->queue.pop_front();
+      s->used_bytes += j->bytes;
+      s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
+      admitted.push_back(j);
+    }
+  }
+  for (Job* j : admitted) {  // outside the lock
+    nmfa_params prm;
+    nmfa_params_default(&prm);
+    prm.precision = s->p.precision;
+    nmfa_ctx* c = nullptr;
+    const int rc = nmfa_create(j->n, j->J.data(), j->h.empty() ? nullptr : j->h.data(), &prm, &c);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (rc != NMFA_OK) {
+      j->msg = nmfa_last_error();
+      finish_job(s, j, rc);
+      s->cv_done.notify_all();
+      continue;
+    }
+    j->ctx = c;
+    std::vector<double>().swap(j->J);
+    std::vector<double>().swap(j->h);
+    j->status = NMFA_JOB_RUNNING;
+    s->active.push_back(j);
+  }
+}
+
 void scheduler(nmfa_server* s) {
   (void)hipSetDevice(s->device);
   std::vector<AnnealArgs> h_args;
   std::vector<int2> h_tasks;
   for (;;) {
-    std::vector<Job*> admitted;
+    bool idle;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
       if (s->stop && s->queue.empty() && s->active.empty()) break;
-      // FIFO admission by budget and slots; the head of the queue is never overtaken
-      while (!s->queue.empty() && (int)(s->active.size() + admitted.size()) < s->p.max_active) {
-        Job* j = s->queue.front();
-        if (j->bytes > s->p.hbm_budget_bytes) {
-          s->queue.pop_front();
-          j->msg = "request needs more device memory than the whole budget";
-          j->bytes = 0;  // never charged to the budget
-          finish_job(s, j, NMFA_ENOMEM);
-          s->cv_done.notify_all();
-          continue;
-        }
-        if (s->used_bytes + j->bytes > s->p.hbm_budget_bytes) break;
-        s->queue.pop_front();
-        s->used_bytes += j->bytes;
-        s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
-        admitted.push_back(j);
-      }
+      idle = s->active.empty();
     }
-    // upload the admitted instances (outside the lock)
-    for (Job* j : admitted) {
-      nmfa_params prm;
-      nmfa_params_default(&prm);
-      prm.precision = s->p.precision;
-      nmfa_ctx* c = nullptr;
-      const int rc = nmfa_create(j->n, j->J.data(), j->h.empty() ? nullptr : j->h.data(), &prm, &c);
-      std::lock_guard<std::mutex> lk(s->mu);
-      if (rc != NMFA_OK) {
-        j->msg = nmfa_last_error();
-        finish_job(s, j, rc);
-        s->cv_done.notify_all();
-        continue;
-      }
-      j->ctx = c;
-      std::vector<double>().swap(j->J);
-      std::vector<double>().swap(j->h);
-      j->status = NMFA_JOB_RUNNING;
-      s->active.push_back(j);
-    }
+    if (idle) admit_queued(s);  // nothing runs yet to overlap the uploads with
 
     // ---- one round ---------------------------------------------------------------------
     std::vector<Job*> round_jobs;
@@ -260,12 +318,14 @@ void scheduler(nmfa_server* s) {
     }
     int spread = 0;
     std::vector<hipStream_t> stream_of(round_jobs.size(), s->stream);
+    std::vector<int> group_lane, group_cap;
+    plan_group_lanes(s, round_jobs, t_end_of, &group_lane, &group_cap);
     for (size_t k = 0; k < round_jobs.size() && rc == NMFA_OK; ++k) {
       Job* j = round_jobs[k];
       if (!j->ctx || j->ctx->path == 0) continue;
       const int te = t_end_of[k];
-      stream_of[k] = j->ctx->path == 2 ? s->lanes[0] : s->lanes[1 + (spread++ % (SERVER_LANES - 1))];
-      int r2 = ctx_launch_run(j->ctx, j->R, j->t_f, j->t_done + 1, te, j->seed, stream_of[k], false);
+      stream_of[k] = group_lane[k] >= 0 ? s->lanes[group_lane[k]] : s->lanes[1 + (spread++ % (SERVER_LANES - 1))];
+      int r2 = ctx_launch_run(j->ctx, j->R, j->t_f, j->t_done + 1, te, j->seed, stream_of[k], false, group_cap[k]);
       if (r2 != NMFA_OK) {
         std::lock_guard<std::mutex> lk(s->mu);
         j->msg = nmfa_last_error();
@@ -284,6 +344,8 @@ void scheduler(nmfa_server* s) {
         done.push_back(j);
       }
     }
+    // requests admitted now upload while the round runs and join the next one
+    if (rc == NMFA_OK) admit_queued(s);
     hipError_t se = hipStreamSynchronize(s->stream);
     for (hipStream_t ls : s->lanes) {
       const hipError_t e = hipStreamSynchronize(ls);
@@ -340,8 +402,10 @@ extern "C" int nmfa_server_create(const nmfa_server_params* p, nmfa_server** out
     return nmfa_fail(NMFA_EINVAL, "nmfa_server_create: invalid parameters");
   nmfa_server* s = new nmfa_server();
   s->p = *p;
-  bool ok = hipGetDevice(&s->device) == hipSuccess && hipStreamCreate(&s->stream) == hipSuccess;
-  for (hipStream_t& ls : s->lanes) ok = ok && hipStreamCreate(&ls) == hipSuccess;
+  // non-blocking streams: uploads of newly admitted requests (null stream) overlap the running round
+  bool ok = hipGetDevice(&s->device) == hipSuccess &&
+            hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+  for (hipStream_t& ls : s->lanes) ok = ok && hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     for (hipStream_t ls : s->lanes)
       if (ls) (void)hipStreamDestroy(ls);
@@ -349,6 +413,8 @@ extern "C" int nmfa_server_create(const nmfa_server_params* p, nmfa_server** out
     delete s;
     return nmfa_fail(NMFA_EDEVICE, "nmfa_server_create: no HIP device / stream");
   }
+  if (hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess || s->cus < 8)
+    s->cus = 8;
   s->worker = std::thread(scheduler, s);
   *out = s;
   return NMFA_OK;

@@ -130,3 +130,27 @@ def test_large_jobs_side_by_side(nmfa):
             assert np.array_equal(srv.result(t)["E"], E)
         st = srv.stats()
         assert st["completed"] == len(jobs) and st["failed"] == 0
+
+
+def test_group_requests_side_by_side_with_capped_launches(nmfa):
+    # several dense requests on the XCD-group kernels in the same rounds: they run on different
+    # streams under per-stream workgroup budgets, and the largest (16 groups of 12 workgroups)
+    # needs more than one launch under any budget below the whole chip; each result is the one
+    # the request gets alone, bit for bit
+    specs = [(1500, 1024, 260), (900, 512, 240), (2000, 300, 220), (1100, 64, 250), (700, 200, 230)]
+    jobs = [(instances.sk(n, 90 + k), R, t_f, 9100 + k) for k, (n, R, t_f) in enumerate(specs)]
+    alone = []
+    for inst, R, t_f, seed in jobs:
+        with nmfa.Solver(inst.J, inst.h, precision="bf16") as s:
+            s.anneal(R, t_f, seed)
+            assert s.info()["path"].startswith("xcd_rj")
+            alone.append((s.energies()[0], s.spins()))
+    with nmfa.Server(precision="bf16", max_active=64, chunk_iters=80) as srv:
+        tickets = [srv.submit(inst.J, inst.h, R, t_f, seed) for inst, R, t_f, seed in jobs]
+        for (E, sp), t in zip(alone, tickets):
+            assert srv.wait(t, 120000)
+            res = srv.result(t, spins=True)
+            assert np.array_equal(res["E"], E)
+            assert np.array_equal(res["spins"], sp)
+        st = srv.stats()
+        assert st["completed"] == len(jobs) and st["failed"] == 0
