@@ -789,12 +789,15 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     const int per_launch = std::max(1, width / P);
     HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[t_begin & 1], c->n, R, c->Kp, c->Ks, G * Rg,
                               t_begin == 1 ? 1 : 0, st));
-    HIP_TRY(hipMemsetAsync(c->d_ctl, 0, (size_t)xcd_ctl_words() * 4, st));
+    // A new run clears the whole control block; a continued one (and every launch after the
+    // first) only the registration and barrier counters, so that an abort in an earlier chunk of
+    // the run stays raised, ends the later ones at once, and is reported when the run is read.
+    if (t_begin == 1) HIP_TRY(hipMemsetAsync(c->d_ctl, 0, (size_t)xcd_ctl_words() * 4, st));
     HIP_TRY(hipEventRecord(c->ev0, st));
     c->launches = 0;
     for (int gb = 0; gb < G; gb += per_launch) {
       const int ng = std::min(per_launch, G - gb);
-      if (gb > 0) {  // fresh registration and barrier counters; the abort and mode words persist
+      if (gb > 0 || t_begin > 1) {  // fresh registration and barrier counters; abort and mode persist
         HIP_TRY(hipMemsetAsync(c->d_ctl, 0, 17 * 4, st));
         HIP_TRY(hipMemsetAsync(c->d_ctl + 64, 0, (size_t)(xcd_ctl_words() - 64) * 4, st));
       }
@@ -838,10 +841,17 @@ extern "C" int nmfa_anneal(nmfa_ctx* c, int32_t R, int32_t t_f, uint64_t seed, v
   return nmfa_anneal_range(c, R, t_f, 1, t_f, seed, hip_stream);
 }
 
+static int check_ctl(nmfa_ctx* c);
+
 static int sync_ctx(nmfa_ctx* c) {
   HIP_TRY(hipSetDevice(c->device));
   if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
   else HIP_TRY(hipDeviceSynchronize());
+  return check_ctl(c);
+}
+
+// After the work of a run has completed: the XCD-group kernels' abort and exchange-mode words.
+static int check_ctl(nmfa_ctx* c) {
   if (c->ctl_pending) {
     unsigned flags[3] = {0, 0, 0};
     HIP_TRY(hipMemcpy(flags, c->d_ctl + 16, sizeof(flags), hipMemcpyDeviceToHost));
@@ -853,6 +863,20 @@ static int sync_ctx(nmfa_ctx* c) {
       return fail(NMFA_EDEVICE, "XCD-group kernel: a group barrier or the start-up registration timed out");
     }
   }
+  return NMFA_OK;
+}
+
+int ctx_read_results(nmfa_ctx* c, double* E, int64_t* E_int, int8_t* spins) {
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipEventSynchronize(c->ev1));
+  int rc = check_ctl(c);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(E, c->d_E, (size_t)c->R * 8, hipMemcpyDeviceToHost));
+  if (c->J_integral && c->h_integral && c->d_J8)
+    HIP_TRY(hipMemcpy(E_int, c->d_Eint, (size_t)c->R * 8, hipMemcpyDeviceToHost));
+  else
+    std::memset(E_int, 0, (size_t)c->R * 8);
+  HIP_TRY(hipMemcpy(spins, c->d_spins, (size_t)c->R * c->n, hipMemcpyDeviceToHost));
   return NMFA_OK;
 }
 

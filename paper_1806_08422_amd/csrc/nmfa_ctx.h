@@ -86,6 +86,10 @@ bool ctx_group_shape(const nmfa_ctx* c, int32_t R, int* P, int* G);
 // other on st, cover the remaining groups); results do not depend on it.
 int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t t_end, uint64_t seed,
                    hipStream_t st, bool finish, int max_workgroups = 0);
+// Energies (E_int zero unless exact) and spins of a run whose energies were enqueued by
+// ctx_finish_run: waits for that run's own completion event rather than its stream, which may
+// already hold later work, then checks the group kernels' abort word. All pointers are host.
+int ctx_read_results(nmfa_ctx* c, double* E, int64_t* E_int, int8_t* spins);
 // Enqueue the energies of the readout and mark the results valid.
 int ctx_finish_run(nmfa_ctx* c, hipStream_t st);
 // Record an error message for nmfa_last_error() and return code.

@@ -57,8 +57,13 @@ struct Job {
   size_t bytes = 0;          // device memory charged to the budget
   int status = NMFA_JOB_QUEUED;  // or a negative error code once failed / cancelled
   bool cancel = false;
+  bool failed = false;       // a chunk could not be enqueued: ends as a device error
   nmfa_ctx* ctx = nullptr;
-  int t_done = 0;
+  int t_done = 0;            // iterations complete on the device
+  int t_sched = 0;           // iterations enqueued (up to two chunks ahead of t_done)
+  int lane = -2;             // stream of the last enqueued chunk: -1 batched stream, 0.. lanes
+  hipEvent_t ev = nullptr;   // recorded after the last enqueued chunk
+  uint64_t last_round = 0;   // round of the last enqueued chunk
   std::vector<double> E;
   std::vector<int64_t> Eint;
   std::vector<int8_t> spins;
@@ -84,6 +89,31 @@ size_t job_bytes(int n, int R, int t_f, bool j_integral) {
 
 constexpr int SERVER_LANES = 3;  // streams besides the batched launch's (4 hardware queues in all)
 
+// One round of the pipeline: the chunk of every request advanced in it, and what the host keeps
+// until the round's work is complete (the batched launch's staging).
+struct Round {
+  bool inflight = false;
+  uint64_t id = 0;
+  std::vector<Job*> ran;
+  std::vector<int> t_end;      // parallel to ran
+  std::vector<char> last;      // parallel to ran: the request's final chunk (energies enqueued)
+  hipEvent_t ev[1 + SERVER_LANES] = {};  // end of the round on every stream
+  std::vector<AnnealArgs> h_args;
+  std::vector<int2> h_tasks;
+  AnnealArgs* d_jobs = nullptr;
+  int cap_jobs = 0;
+  int2* d_tasks = nullptr;
+  int cap_tasks = 0;
+};
+
+// A finished request's device state, kept until it can be freed without stalling the pipeline
+// (freeing device memory waits for the device).
+struct Retired {
+  nmfa_ctx* ctx;
+  hipEvent_t ev;
+  size_t bytes;
+};
+
 struct nmfa_server {
   nmfa_server_params p{};
   int device = 0;
@@ -99,10 +129,14 @@ struct nmfa_server {
   uint64_t next_id = 1;
   bool stop = false;
   std::thread worker;
-  AnnealArgs* d_jobs = nullptr;
-  int cap_jobs = 0;
-  int2* d_tasks = nullptr;
-  int cap_tasks = 0;
+  Round rounds[2];
+  uint64_t next_round = 1, completed_round = 0;
+  std::vector<Retired> retired;            // scheduler thread only
+  size_t retired_bytes = 0;
+  hipEvent_t ev_group[SERVER_LANES] = {};  // after the last group launch on each lane
+  bool group_rec[SERVER_LANES] = {};
+  hipEvent_t ev_wide = nullptr;            // after the last whole-chip group launch
+  bool wide_rec = false;
   nmfa_server_stats st{};
 };
 
@@ -118,15 +152,19 @@ extern "C" void nmfa_server_params_default(nmfa_server_params* p) {
 
 namespace {
 
-// Finish a request (under the lock): record the outcome, free its device memory and budget.
+// Finish a request (under the lock, with none of its work in flight): record the outcome and
+// retire its device state; its memory stays charged to the budget until free_retired.
 void finish_job(nmfa_server* s, Job* j, int status) {
   if (j->ctx) {
-    nmfa_destroy(j->ctx);
+    s->retired.push_back(Retired{j->ctx, j->ev, j->bytes});
+    s->retired_bytes += j->bytes;
     j->ctx = nullptr;
+    j->ev = nullptr;
+  } else {
+    s->used_bytes -= std::min(s->used_bytes, j->bytes);
   }
   j->status = status;
   j->t_finish = now_s();
-  s->used_bytes -= std::min(s->used_bytes, j->bytes);
   if (status == NMFA_JOB_DONE) ++s->st.completed;
   else if (status == NMFA_ECANCELED) ++s->st.cancelled;
   else ++s->st.failed;
@@ -150,7 +188,7 @@ void plan_group_lanes(const nmfa_server* s, const std::vector<Job*>& jobs, const
   if (idx.size() < 2 || budget[1] < 8) return;
   for (int k : idx)
     if (P[k] > budget[0]) return;
-  auto iters = [&](int k) { return (double)(t_end[k] - jobs[k]->t_done); };
+  auto iters = [&](int k) { return (double)(t_end[k] - jobs[k]->t_sched); };
   std::sort(idx.begin(), idx.end(), [&](int x, int y) {
     return (double)G[x] * P[x] * jobs[x]->ctx->Mp * iters(x) > (double)G[y] * P[y] * jobs[y]->ctx->Mp * iters(y);
   });
@@ -174,29 +212,50 @@ void plan_group_lanes(const nmfa_server* s, const std::vector<Job*>& jobs, const
   }
 }
 
-int ensure_staging(nmfa_server* s, int n_jobs, int n_tasks) {
-  if (n_jobs > s->cap_jobs) {
-    (void)hipFree(s->d_jobs);
-    s->d_jobs = nullptr;
-    const int cap = std::max(n_jobs, 2 * s->cap_jobs);
-    if (hipMalloc(&s->d_jobs, sizeof(AnnealArgs) * cap) != hipSuccess) return NMFA_ENOMEM;
-    s->cap_jobs = cap;
+int ensure_staging(Round& r, int n_jobs, int n_tasks) {
+  if (n_jobs > r.cap_jobs) {
+    (void)hipFree(r.d_jobs);
+    r.d_jobs = nullptr;
+    const int cap = std::max(n_jobs, 2 * r.cap_jobs);
+    if (hipMalloc(&r.d_jobs, sizeof(AnnealArgs) * cap) != hipSuccess) return NMFA_ENOMEM;
+    r.cap_jobs = cap;
   }
-  if (n_tasks > s->cap_tasks) {
-    (void)hipFree(s->d_tasks);
-    s->d_tasks = nullptr;
-    const int cap = std::max(n_tasks, 2 * s->cap_tasks);
-    if (hipMalloc(&s->d_tasks, sizeof(int2) * cap) != hipSuccess) return NMFA_ENOMEM;
-    s->cap_tasks = cap;
+  if (n_tasks > r.cap_tasks) {
+    (void)hipFree(r.d_tasks);
+    r.d_tasks = nullptr;
+    const int cap = std::max(n_tasks, 2 * r.cap_tasks);
+    if (hipMalloc(&r.d_tasks, sizeof(int2) * cap) != hipSuccess) return NMFA_ENOMEM;
+    r.cap_tasks = cap;
   }
   return NMFA_OK;
 }
 
+// Free the retired requests' device state and release their budget. Waits for the work in
+// flight (freeing device memory does), so it runs when the pipeline is empty or memory is needed.
+void free_retired(nmfa_server* s) {
+  std::vector<Retired> rs;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    rs.swap(s->retired);
+  }
+  size_t freed = 0;
+  for (const Retired& r : rs) {
+    nmfa_destroy(r.ctx);
+    if (r.ev) (void)hipEventDestroy(r.ev);
+    freed += r.bytes;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->used_bytes -= std::min(s->used_bytes, freed);
+  s->retired_bytes -= std::min(s->retired_bytes, freed);
+}
+
 // Admit queued requests (FIFO by device memory budget and slots; the head of the queue is never
-// overtaken) and upload their instances. Runs while the previous round's kernels execute: the
-// server's streams do not synchronise with the null stream that the uploads use.
-void admit_queued(nmfa_server* s) {
+// overtaken) and upload their instances. Runs while rounds execute: the server's streams do not
+// synchronise with the null stream that the uploads use. Returns true when the head of the queue
+// waits for memory that freeing the retired requests would release.
+bool admit_queued(nmfa_server* s) {
   std::vector<Job*> admitted;
+  bool want_free = false;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     while (!s->queue.empty() && (int)(s->active.size() + admitted.size()) < s->p.max_active) {
@@ -209,7 +268,10 @@ void admit_queued(nmfa_server* s) {
         s->cv_done.notify_all();
         continue;
       }
-      if (s->used_bytes + j->bytes > s->p.hbm_budget_bytes) break;
+      if (s->used_bytes + j->bytes > s->p.hbm_budget_bytes) {
+        want_free = s->retired_bytes > 0;
+        break;
+      }
       s->queue.pop_front();
       s->used_bytes += j->bytes;
       s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
@@ -221,7 +283,13 @@ void admit_queued(nmfa_server* s) {
     nmfa_params_default(&prm);
     prm.precision = s->p.precision;
     nmfa_ctx* c = nullptr;
-    const int rc = nmfa_create(j->n, j->J.data(), j->h.empty() ? nullptr : j->h.data(), &prm, &c);
+    int rc = nmfa_create(j->n, j->J.data(), j->h.empty() ? nullptr : j->h.data(), &prm, &c);
+    if (rc == NMFA_OK && hipEventCreateWithFlags(&j->ev, hipEventDisableTiming) != hipSuccess) {
+      nmfa_destroy(c);
+      c = nullptr;
+      j->ev = nullptr;
+      rc = nmfa_fail(NMFA_EDEVICE, "server: event creation failed");
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (rc != NMFA_OK) {
       j->msg = nmfa_last_error();
@@ -235,160 +303,261 @@ void admit_queued(nmfa_server* s) {
     j->status = NMFA_JOB_RUNNING;
     s->active.push_back(j);
   }
+  return want_free;
+}
+
+// Enqueue the next chunk of every running request into round r (nothing if none has iterations
+// left to enqueue). A request's chunks follow each other on one stream or, when its stream
+// changes, through its event.
+void enqueue_round(nmfa_server* s, Round& r) {
+  r.ran.clear();
+  r.t_end.clear();
+  r.last.clear();
+  r.h_args.clear();
+  r.h_tasks.clear();
+  std::vector<Job*> jobs;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<Job*> keep;
+    for (Job* j : s->active) {
+      if (j->cancel && j->last_round <= s->completed_round) {  // nothing of it in flight
+        finish_job(s, j, j->failed ? NMFA_EDEVICE : NMFA_ECANCELED);
+        s->cv_done.notify_all();
+        continue;
+      }
+      keep.push_back(j);
+      if (!j->cancel && j->t_sched < j->t_f) jobs.push_back(j);
+    }
+    s->active.swap(keep);
+  }
+  if (jobs.empty()) return;
+  r.id = s->next_round++;
+  std::vector<int> te(jobs.size());
+  for (size_t k = 0; k < jobs.size(); ++k) te[k] = std::min(jobs[k]->t_sched + s->p.chunk_iters, jobs[k]->t_f);
+  std::vector<Job*> failed;
+  auto fail_job = [&](Job* j) {
+    j->msg = nmfa_last_error();
+    failed.push_back(j);
+  };
+  auto ran = [&](Job* j, int t_end, int lane, hipStream_t st) {
+    j->t_sched = t_end;
+    j->lane = lane;
+    j->last_round = r.id;
+    j->ctx->state_valid = true;  // the next chunk, enqueued behind this one, resumes from its state
+    bool last = t_end == j->t_f;
+    if (last && ctx_finish_run(j->ctx, st) != NMFA_OK) {
+      last = false;
+      fail_job(j);
+    }
+    (void)hipEventRecord(j->ev, st);
+    r.ran.push_back(j);
+    r.t_end.push_back(t_end);
+    r.last.push_back(last ? 1 : 0);
+  };
+
+  // requests on the persistent small-N path: one batched launch
+  int max_Mp = 0;
+  size_t lds = 0;
+  std::vector<std::pair<Job*, int>> batched;
+  for (size_t k = 0; k < jobs.size(); ++k) {
+    Job* j = jobs[k];
+    if (j->ctx->path != 0) continue;
+    AnnealArgs a{};
+    if (ctx_prepare_run(j->ctx, j->R, j->t_f, j->t_sched + 1, te[k], j->seed, s->stream, &a) != NMFA_OK) {
+      fail_job(j);
+      continue;
+    }
+    const int job_index = (int)r.h_args.size();
+    r.h_args.push_back(a);
+    for (int b = 0; b < (j->R + 15) / 16; ++b) r.h_tasks.push_back(make_int2(job_index, b));
+    max_Mp = std::max(max_Mp, j->ctx->Mp);
+    lds = std::max(lds, small_lds_bytes(j->ctx->prec, j->ctx->Mp, j->ctx->lds_stride));
+    batched.emplace_back(j, te[k]);
+  }
+  if (!batched.empty()) {
+    const bool ok =
+        ensure_staging(r, (int)r.h_args.size(), (int)r.h_tasks.size()) == NMFA_OK &&
+        hipMemcpyAsync(r.d_jobs, r.h_args.data(), sizeof(AnnealArgs) * r.h_args.size(), hipMemcpyHostToDevice,
+                       s->stream) == hipSuccess &&
+        hipMemcpyAsync(r.d_tasks, r.h_tasks.data(), sizeof(int2) * r.h_tasks.size(), hipMemcpyHostToDevice,
+                       s->stream) == hipSuccess &&
+        launch_anneal_small_batched(s->p.precision, r.d_jobs, r.d_tasks, (int)r.h_tasks.size(), max_Mp, lds,
+                                    s->stream) == hipSuccess;
+    if (ok) {
+      ++s->st.batched_launches;
+      for (auto& jt : batched) ran(jt.first, jt.second, -1, s->stream);
+    } else {
+      (void)nmfa_fail(NMFA_EDEVICE, "server: batched launch failed");
+      for (auto& jt : batched) fail_job(jt.first);
+    }
+  }
+
+  // the others on their own kernels, over the lanes
+  std::vector<int> group_lane, group_cap;
+  plan_group_lanes(s, jobs, te, &group_lane, &group_cap);
+  for (size_t k = 0; k < jobs.size(); ++k) {
+    Job* j = jobs[k];
+    if (j->ctx->path == 0) continue;
+    const bool group = group_lane[k] >= 0;
+    const int lane = group ? group_lane[k] : 1 + (int)(j->id % (SERVER_LANES - 1));
+    hipStream_t st = s->lanes[lane];
+    if (j->lane != lane && j->lane != -2) (void)hipStreamWaitEvent(st, j->ev, 0);
+    if (group) {
+      // group launches side by side must fit on the chip together: a whole-chip launch waits for
+      // the other lanes' group launches, and later group launches on them wait for it
+      if (group_cap[k] == 0) {
+        for (int L = 0; L < SERVER_LANES; ++L)
+          if (L != lane && s->group_rec[L]) (void)hipStreamWaitEvent(st, s->ev_group[L], 0);
+      } else if (s->wide_rec) {
+        (void)hipStreamWaitEvent(st, s->ev_wide, 0);
+      }
+    }
+    if (ctx_launch_run(j->ctx, j->R, j->t_f, j->t_sched + 1, te[k], j->seed, st, false, group_cap[k]) != NMFA_OK) {
+      fail_job(j);
+      continue;
+    }
+    if (group) {
+      (void)hipEventRecord(s->ev_group[lane], st);
+      s->group_rec[lane] = true;
+      if (group_cap[k] == 0) {
+        (void)hipEventRecord(s->ev_wide, st);
+        s->wide_rec = true;
+      }
+    }
+    ran(j, te[k], lane, st);
+  }
+  (void)hipEventRecord(r.ev[0], s->stream);
+  for (int L = 0; L < SERVER_LANES; ++L) (void)hipEventRecord(r.ev[1 + L], s->lanes[L]);
+  r.inflight = true;
+  if (!failed.empty()) {
+    // a request whose chunk could not be enqueued fails once nothing of it is in flight
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (Job* j : failed) {
+      j->cancel = true;
+      j->failed = true;
+    }
+  }
+}
+
+// Wait for round r and hand over its results: requests whose final chunk it held return their
+// energies and spins; cancelled or failed requests with nothing left in flight are retired.
+// Returns false on a device error.
+bool complete_round(nmfa_server* s, Round& r) {
+  hipError_t se = hipSuccess;
+  for (hipEvent_t e : r.ev) {
+    const hipError_t x = hipEventSynchronize(e);
+    if (se == hipSuccess) se = x;
+  }
+  r.inflight = false;
+  std::vector<char> ok(r.ran.size(), 0);
+  for (size_t k = 0; k < r.ran.size(); ++k) {
+    Job* j = r.ran[k];
+    j->t_done = r.t_end[k];
+    if (r.last[k] && se == hipSuccess && !j->cancel) {
+      j->E.resize(j->R);
+      j->Eint.resize(j->R);
+      j->spins.resize((size_t)j->R * j->n);
+      const int r3 = ctx_read_results(j->ctx, j->E.data(), j->Eint.data(), j->spins.data());
+      ok[k] = r3 == NMFA_OK ? 1 : 0;
+      if (r3 != NMFA_OK) j->msg = nmfa_last_error();
+    }
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  ++s->st.rounds;
+  s->completed_round = r.id;
+  bool notify = false;
+  for (size_t k = 0; k < r.ran.size(); ++k) {
+    Job* j = r.ran[k];
+    if (j->last_round != r.id) continue;  // a later chunk is in flight
+    if (se != hipSuccess) {
+      j->msg = hipGetErrorString(se);
+      finish_job(s, j, NMFA_EDEVICE);
+    } else if (j->cancel) {
+      finish_job(s, j, j->failed ? NMFA_EDEVICE : NMFA_ECANCELED);
+    } else if (r.last[k]) {
+      finish_job(s, j, ok[k] ? NMFA_JOB_DONE : NMFA_EDEVICE);
+    } else {
+      continue;
+    }
+    notify = true;
+  }
+  std::vector<Job*> keep;
+  for (Job* j : s->active)
+    if (j->ctx) keep.push_back(j);
+  s->active.swap(keep);
+  if (notify) s->cv_done.notify_all();
+  return se == hipSuccess;
 }
 
 void scheduler(nmfa_server* s) {
   (void)hipSetDevice(s->device);
-  std::vector<AnnealArgs> h_args;
-  std::vector<int2> h_tasks;
+  constexpr size_t kRetireBatch = 64;
   for (;;) {
-    bool idle;
+    const bool busy = s->rounds[0].inflight || s->rounds[1].inflight;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
-      if (s->stop && s->queue.empty() && s->active.empty()) break;
-      idle = s->active.empty();
+      if (!busy) s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
+      if (s->stop && s->queue.empty() && s->active.empty() && !busy) break;
     }
-    if (idle) admit_queued(s);  // nothing runs yet to overlap the uploads with
-
-    // ---- one round ---------------------------------------------------------------------
-    std::vector<Job*> round_jobs;
+    if (!busy) {  // nothing runs to overlap with: free, then admit
+      free_retired(s);
+      (void)admit_queued(s);
+    }
+    // round k+1 is enqueued before round k is waited for, so that the device has the next round
+    // queued while the host collects results and admits requests
+    Round& r = s->rounds[s->rounds[0].inflight ? 1 : 0];
+    Round& other = s->rounds[&r == &s->rounds[0] ? 1 : 0];
+    enqueue_round(s, r);
+    const bool want_free = admit_queued(s);
+    Round* wait = nullptr;
+    if (r.inflight && other.inflight) wait = other.id < r.id ? &other : &r;
+    else if (!r.inflight && other.inflight) wait = &other;
+    if (wait && !complete_round(s, *wait)) {
+      // after a device error, drain the other round too; its requests fail with it
+      Round& o = wait == &r ? other : r;
+      if (o.inflight) {
+        {
+          std::lock_guard<std::mutex> lk(s->mu);
+          for (Job* j : o.ran) {
+            j->cancel = true;
+            j->failed = true;
+            if (j->msg.empty()) j->msg = "device error in the previous round";
+          }
+        }
+        (void)complete_round(s, o);
+      }
+    }
+    size_t n_retired;
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      std::vector<Job*> keep;
-      for (Job* j : s->active) {
-        if (j->cancel) {
-          finish_job(s, j, NMFA_ECANCELED);
-          s->cv_done.notify_all();
-        } else {
-          keep.push_back(j);
-        }
-      }
-      s->active.swap(keep);
-      round_jobs = s->active;
+      n_retired = s->retired.size();
     }
-    if (round_jobs.empty()) continue;
-
-    int rc = NMFA_OK;
-    std::vector<Job*> ran;
-    std::vector<int> t_end_of(round_jobs.size());
-    h_args.clear();
-    h_tasks.clear();
-    int max_Mp = 0;
-    size_t lds = 0;
-    int prec = s->p.precision;
-    std::vector<Job*> batched;
-    for (size_t k = 0; k < round_jobs.size(); ++k) {
-      Job* j = round_jobs[k];
-      const int tb = j->t_done + 1;
-      const int te = std::min(j->t_done + s->p.chunk_iters, j->t_f);
-      t_end_of[k] = te;
-      if (j->ctx->path == 0) {
-        AnnealArgs a{};
-        int r2 = ctx_prepare_run(j->ctx, j->R, j->t_f, tb, te, j->seed, s->stream, &a);
-        if (r2 != NMFA_OK) {
-          std::lock_guard<std::mutex> lk(s->mu);
-          j->msg = nmfa_last_error();
-          finish_job(s, j, r2);
-          s->cv_done.notify_all();
-          continue;
-        }
-        const int job_index = (int)h_args.size();
-        h_args.push_back(a);
-        for (int b = 0; b < (j->R + 15) / 16; ++b) h_tasks.push_back(make_int2(job_index, b));
-        max_Mp = std::max(max_Mp, j->ctx->Mp);
-        lds = std::max(lds, small_lds_bytes(j->ctx->prec, j->ctx->Mp, j->ctx->lds_stride));
-        batched.push_back(j);
-      }
+    if (want_free || n_retired >= kRetireBatch) {
+      free_retired(s);
+      if (want_free) (void)admit_queued(s);
     }
-    if (!batched.empty()) {
-      rc = ensure_staging(s, (int)h_args.size(), (int)h_tasks.size());
-      if (rc == NMFA_OK &&
-          (hipMemcpyAsync(s->d_jobs, h_args.data(), sizeof(AnnealArgs) * h_args.size(), hipMemcpyHostToDevice,
-                          s->stream) != hipSuccess ||
-           hipMemcpyAsync(s->d_tasks, h_tasks.data(), sizeof(int2) * h_tasks.size(), hipMemcpyHostToDevice,
-                          s->stream) != hipSuccess ||
-           launch_anneal_small_batched(prec, s->d_jobs, s->d_tasks, (int)h_tasks.size(), max_Mp, lds, s->stream) !=
-               hipSuccess))
-        rc = NMFA_EDEVICE;
-      if (rc == NMFA_OK) {
-        ++s->st.batched_launches;
-        for (Job* j : batched) ran.push_back(j);
-      }
-    }
-    int spread = 0;
-    std::vector<hipStream_t> stream_of(round_jobs.size(), s->stream);
-    std::vector<int> group_lane, group_cap;
-    plan_group_lanes(s, round_jobs, t_end_of, &group_lane, &group_cap);
-    for (size_t k = 0; k < round_jobs.size() && rc == NMFA_OK; ++k) {
-      Job* j = round_jobs[k];
-      if (!j->ctx || j->ctx->path == 0) continue;
-      const int te = t_end_of[k];
-      stream_of[k] = group_lane[k] >= 0 ? s->lanes[group_lane[k]] : s->lanes[1 + (spread++ % (SERVER_LANES - 1))];
-      int r2 = ctx_launch_run(j->ctx, j->R, j->t_f, j->t_done + 1, te, j->seed, stream_of[k], false, group_cap[k]);
-      if (r2 != NMFA_OK) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        j->msg = nmfa_last_error();
-        finish_job(s, j, r2);
-        s->cv_done.notify_all();
-        continue;
-      }
-      ran.push_back(j);
-    }
-    // energies of the requests that complete in this round
-    std::vector<Job*> done;
-    for (Job* j : ran) {
-      const size_t k = std::find(round_jobs.begin(), round_jobs.end(), j) - round_jobs.begin();
-      if (t_end_of[k] == j->t_f) {
-        if (ctx_finish_run(j->ctx, stream_of[k]) != NMFA_OK) rc = NMFA_EDEVICE;
-        done.push_back(j);
-      }
-    }
-    // requests admitted now upload while the round runs and join the next one
-    if (rc == NMFA_OK) admit_queued(s);
-    hipError_t se = hipStreamSynchronize(s->stream);
-    for (hipStream_t ls : s->lanes) {
-      const hipError_t e = hipStreamSynchronize(ls);
-      if (se == hipSuccess) se = e;
-    }
-    ++s->st.rounds;
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (rc != NMFA_OK || se != hipSuccess) {
-      // a device failure ends every request of the round
-      for (Job* j : ran) {
-        j->msg = se != hipSuccess ? hipGetErrorString(se) : "launch failed in the scheduler";
-        finish_job(s, j, NMFA_EDEVICE);
-      }
-      std::vector<Job*> keep;
-      for (Job* j : s->active)
-        if (j->ctx) keep.push_back(j);
-      s->active.swap(keep);
-      s->cv_done.notify_all();
-      continue;
-    }
-    for (Job* j : ran) {
-      const size_t k = std::find(round_jobs.begin(), round_jobs.end(), j) - round_jobs.begin();
-      j->t_done = t_end_of[k];
-      j->ctx->state_valid = true;  // the next round resumes from this state
-    }
-    for (Job* j : done) {
-      j->E.resize(j->R);
-      j->Eint.resize(j->R);
-      j->spins.resize((size_t)j->R * j->n);
-      int r3 = nmfa_energies(j->ctx, j->E.data(), j->Eint.data());
-      if (r3 == NMFA_OK) r3 = nmfa_spins(j->ctx, j->spins.data(), 0);
-      if (r3 != NMFA_OK) j->msg = nmfa_last_error();
-      finish_job(s, j, r3 == NMFA_OK ? NMFA_JOB_DONE : r3);
-    }
-    std::vector<Job*> keep;
-    for (Job* j : s->active)
-      if (j->ctx) keep.push_back(j);
-    s->active.swap(keep);
-    if (!done.empty()) s->cv_done.notify_all();
   }
+  free_retired(s);
 }
 
 }  // namespace
+
+// Streams, events and staging of a server whose scheduler thread has ended (or never started).
+static void destroy_server_resources(nmfa_server* s) {
+  for (Round& r : s->rounds) {
+    (void)hipFree(r.d_jobs);
+    (void)hipFree(r.d_tasks);
+    for (hipEvent_t e : r.ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  for (hipEvent_t e : s->ev_group)
+    if (e) (void)hipEventDestroy(e);
+  if (s->ev_wide) (void)hipEventDestroy(s->ev_wide);
+  for (hipStream_t ls : s->lanes)
+    if (ls) (void)hipStreamDestroy(ls);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
 
 extern "C" int nmfa_server_create(const nmfa_server_params* p, nmfa_server** out) {
   if (!out) return nmfa_fail(NMFA_EINVAL, "nmfa_server_create: out is NULL");
@@ -407,14 +576,19 @@ extern "C" int nmfa_server_create(const nmfa_server_params* p, nmfa_server** out
             hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
   for (hipStream_t& ls : s->lanes) ok = ok && hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
-    for (hipStream_t ls : s->lanes)
-      if (ls) (void)hipStreamDestroy(ls);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
-    delete s;
+    destroy_server_resources(s);
     return nmfa_fail(NMFA_EDEVICE, "nmfa_server_create: no HIP device / stream");
   }
   if (hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess || s->cus < 8)
     s->cus = 8;
+  bool ev_ok = hipEventCreateWithFlags(&s->ev_wide, hipEventDisableTiming) == hipSuccess;
+  for (hipEvent_t& e : s->ev_group) ev_ok = ev_ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  for (Round& r : s->rounds)
+    for (hipEvent_t& e : r.ev) ev_ok = ev_ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ev_ok) {
+    destroy_server_resources(s);
+    return nmfa_fail(NMFA_EDEVICE, "nmfa_server_create: event creation failed");
+  }
   s->worker = std::thread(scheduler, s);
   *out = s;
   return NMFA_OK;
@@ -559,11 +733,8 @@ extern "C" void nmfa_server_destroy(nmfa_server* s) {
   if (s->worker.joinable()) s->worker.join();
   for (auto& kv : s->jobs) {
     if (kv.second->ctx) nmfa_destroy(kv.second->ctx);
+    if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
     delete kv.second;
   }
-  (void)hipFree(s->d_jobs);
-  (void)hipFree(s->d_tasks);
-  (void)hipStreamDestroy(s->stream);
-  for (hipStream_t ls : s->lanes) (void)hipStreamDestroy(ls);
-  delete s;
+  destroy_server_resources(s);
 }
