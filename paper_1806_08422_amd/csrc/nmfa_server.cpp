@@ -1,11 +1,12 @@
 // Continuous-batching annealing server (nmfa_server_* in include/nmfa.h).
 //
-// One scheduler thread owns four HIP streams. Requests wait in a FIFO queue; admission is by
-// device memory budget and a cap on concurrently admitted requests. Admitted requests are
-// advanced in rounds of chunk_iters iterations of Algorithm 1:
+// A scheduler thread owns four HIP streams; an admission thread takes requests from a FIFO queue
+// by device memory budget and a cap on concurrently admitted requests, and does their host-side
+// set-up and upload beside the running rounds. Admitted requests advance in rounds of
+// chunk_iters iterations of Algorithm 1:
 //   * all admitted requests on the persistent small-N path share ONE launch per round
 //     (anneal_small_batched over every request's replica blocks; each workgroup reads its own
-//     request's arguments), so newly admitted work overlaps with running work on the device;
+//     request's arguments);
 //   * larger requests advance by the same chunk on their own kernels in the same round, on the
 //     other three streams, so that their kernels run side by side with the batched launch and
 //     with each other. The workgroups of one persistent XCD-group launch wait for each other, so
@@ -15,12 +16,14 @@
 //     budget (a request that needs more takes several launches in turn), and a stream runs one
 //     launch at a time, so the resident group workgroups never exceed the CUs. Requests go to the
 //     stream that would finish them first (largest first). A round with a single group request
-//     gives it the whole chip. The sparse and per-iteration kernels never wait for other
-//     workgroups, so they spread over the second and third streams and at worst delay a group
-//     launch's start;
-//   * between rounds the spin state stays on the device (resuming is bit-exact), finished
-//     requests return their energies/spins and release their memory, and queued requests are
-//     admitted.
+//     gives it the whole chip; such a launch waits for the other streams' group launches, and
+//     theirs for it. The sparse and per-iteration kernels never wait for other workgroups, so
+//     they take the second and third streams and at worst delay a group launch's start;
+//   * two rounds are in flight: round k+1 is enqueued before the host waits for round k, so the
+//     device has work queued while finished requests are read back. A request's consecutive
+//     chunks are ordered by its stream, or by its event when the stream changes. The spin state
+//     stays on the device between chunks (resuming is bit-exact). Finished requests' device
+//     memory is freed in batches, since freeing waits for the device.
 // Every request's arithmetic depends only on that request (counter-based noise keyed by its own
 // seed, replica and iteration), so its result is identical alone and in any mix.
 #include <hip/hip_runtime.h>
@@ -121,14 +124,16 @@ struct nmfa_server {
   hipStream_t lanes[SERVER_LANES] = {};    // group kernels on all three; sparse, per-iteration on [1..]
   int cus = 256;                           // compute units of the device
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_admit, cv_done;  // scheduler, admission thread, clients
   std::deque<Job*> queue;
   std::vector<Job*> active;  // touched by the scheduler thread only (plus stats under mu)
   std::unordered_map<uint64_t, Job*> jobs;
   size_t used_bytes = 0, peak_bytes = 0;
   uint64_t next_id = 1;
   bool stop = false;
-  std::thread worker;
+  std::thread worker, admitter;
+  int admitting = 0;                       // requests whose set-up is under way
+  bool want_free = false;                  // admission waits for memory held by retired requests
   Round rounds[2];
   uint64_t next_round = 1, completed_round = 0;
   std::vector<Retired> retired;            // scheduler thread only
@@ -244,66 +249,92 @@ void free_retired(nmfa_server* s) {
     if (r.ev) (void)hipEventDestroy(r.ev);
     freed += r.bytes;
   }
-  std::lock_guard<std::mutex> lk(s->mu);
-  s->used_bytes -= std::min(s->used_bytes, freed);
-  s->retired_bytes -= std::min(s->retired_bytes, freed);
-}
-
-// Admit queued requests (FIFO by device memory budget and slots; the head of the queue is never
-// overtaken) and upload their instances. Runs while rounds execute: the server's streams do not
-// synchronise with the null stream that the uploads use. Returns true when the head of the queue
-// waits for memory that freeing the retired requests would release.
-bool admit_queued(nmfa_server* s) {
-  std::vector<Job*> admitted;
-  bool want_free = false;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    while (!s->queue.empty() && (int)(s->active.size() + admitted.size()) < s->p.max_active) {
-      Job* j = s->queue.front();
-      if (j->bytes > s->p.hbm_budget_bytes) {
+    s->used_bytes -= std::min(s->used_bytes, freed);
+    s->retired_bytes -= std::min(s->retired_bytes, freed);
+    s->want_free = false;
+  }
+  s->cv_admit.notify_one();
+}
+
+// Whether the head of the queue can be admitted now (or rejected outright); under the lock.
+bool admissible(const nmfa_server* s) {
+  if (s->queue.empty() || (int)s->active.size() + s->admitting >= s->p.max_active) return false;
+  const Job* j = s->queue.front();
+  return j->bytes > s->p.hbm_budget_bytes || s->used_bytes + j->bytes <= s->p.hbm_budget_bytes;
+}
+
+// Admission thread. Admits queued requests (FIFO by device memory budget and slots; the head of
+// the queue is never overtaken) and does their host-side set-up and upload (nmfa_create) beside
+// the scheduler's rounds instead of between them: the server's streams do not synchronise with
+// the null stream that the uploads use. When the head waits for memory that retired requests
+// still hold, it asks the scheduler to free them.
+void admitter(nmfa_server* s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    std::vector<Job*> admitted;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_admit.wait(lk, [&] {
+        if (s->stop || admissible(s)) return true;
+        if (!s->queue.empty() && s->retired_bytes > 0 && !s->want_free &&
+            (int)s->active.size() + s->admitting < s->p.max_active) {
+          s->want_free = true;
+          s->cv_work.notify_one();
+        }
+        return false;
+      });
+      if (s->stop) break;
+      while (admissible(s)) {
+        Job* j = s->queue.front();
         s->queue.pop_front();
-        j->msg = "request needs more device memory than the whole budget";
-        j->bytes = 0;  // never charged to the budget
-        finish_job(s, j, NMFA_ENOMEM);
+        if (j->bytes > s->p.hbm_budget_bytes) {
+          j->msg = "request needs more device memory than the whole budget";
+          j->bytes = 0;  // never charged to the budget
+          finish_job(s, j, NMFA_ENOMEM);
+          s->cv_done.notify_all();
+          continue;
+        }
+        s->used_bytes += j->bytes;
+        s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
+        ++s->admitting;
+        admitted.push_back(j);
+      }
+    }
+    for (Job* j : admitted) {  // outside the lock
+      nmfa_params prm;
+      nmfa_params_default(&prm);
+      prm.precision = s->p.precision;
+      nmfa_ctx* c = nullptr;
+      int rc = nmfa_create(j->n, j->J.data(), j->h.empty() ? nullptr : j->h.data(), &prm, &c);
+      if (rc == NMFA_OK && hipEventCreateWithFlags(&j->ev, hipEventDisableTiming) != hipSuccess) {
+        nmfa_destroy(c);
+        c = nullptr;
+        j->ev = nullptr;
+        rc = nmfa_fail(NMFA_EDEVICE, "server: event creation failed");
+      }
+      std::lock_guard<std::mutex> lk(s->mu);
+      --s->admitting;
+      if (rc != NMFA_OK) {
+        j->msg = nmfa_last_error();
+        finish_job(s, j, rc);
         s->cv_done.notify_all();
         continue;
       }
-      if (s->used_bytes + j->bytes > s->p.hbm_budget_bytes) {
-        want_free = s->retired_bytes > 0;
-        break;
+      j->ctx = c;
+      std::vector<double>().swap(j->J);
+      std::vector<double>().swap(j->h);
+      if (s->stop) {
+        finish_job(s, j, NMFA_ECANCELED);
+        s->cv_done.notify_all();
+        continue;
       }
-      s->queue.pop_front();
-      s->used_bytes += j->bytes;
-      s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
-      admitted.push_back(j);
+      j->status = NMFA_JOB_RUNNING;
+      s->active.push_back(j);
+      s->cv_work.notify_one();
     }
   }
-  for (Job* j : admitted) {  // outside the lock
-    nmfa_params prm;
-    nmfa_params_default(&prm);
-    prm.precision = s->p.precision;
-    nmfa_ctx* c = nullptr;
-    int rc = nmfa_create(j->n, j->J.data(), j->h.empty() ? nullptr : j->h.data(), &prm, &c);
-    if (rc == NMFA_OK && hipEventCreateWithFlags(&j->ev, hipEventDisableTiming) != hipSuccess) {
-      nmfa_destroy(c);
-      c = nullptr;
-      j->ev = nullptr;
-      rc = nmfa_fail(NMFA_EDEVICE, "server: event creation failed");
-    }
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (rc != NMFA_OK) {
-      j->msg = nmfa_last_error();
-      finish_job(s, j, rc);
-      s->cv_done.notify_all();
-      continue;
-    }
-    j->ctx = c;
-    std::vector<double>().swap(j->J);
-    std::vector<double>().swap(j->h);
-    j->status = NMFA_JOB_RUNNING;
-    s->active.push_back(j);
-  }
-  return want_free;
 }
 
 // Enqueue the next chunk of every running request into round r (nothing if none has iterations
@@ -449,11 +480,15 @@ bool complete_round(nmfa_server* s, Round& r) {
     if (se == hipSuccess) se = x;
   }
   r.inflight = false;
-  std::vector<char> ok(r.ran.size(), 0);
+  std::vector<char> ok(r.ran.size(), 0), read(r.ran.size(), 0);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);  // cancel flags are set by clients
+    for (size_t k = 0; k < r.ran.size(); ++k) read[k] = r.last[k] && !r.ran[k]->cancel;
+  }
   for (size_t k = 0; k < r.ran.size(); ++k) {
     Job* j = r.ran[k];
     j->t_done = r.t_end[k];
-    if (r.last[k] && se == hipSuccess && !j->cancel) {
+    if (read[k] && se == hipSuccess) {
       j->E.resize(j->R);
       j->Eint.resize(j->R);
       j->spins.resize((size_t)j->R * j->n);
@@ -485,7 +520,10 @@ bool complete_round(nmfa_server* s, Round& r) {
   for (Job* j : s->active)
     if (j->ctx) keep.push_back(j);
   s->active.swap(keep);
-  if (notify) s->cv_done.notify_all();
+  if (notify) {
+    s->cv_done.notify_all();
+    s->cv_admit.notify_one();
+  }
   return se == hipSuccess;
 }
 
@@ -494,21 +532,17 @@ void scheduler(nmfa_server* s) {
   constexpr size_t kRetireBatch = 64;
   for (;;) {
     const bool busy = s->rounds[0].inflight || s->rounds[1].inflight;
+    if (!busy) free_retired(s);  // nothing in flight: freeing stalls nothing
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      if (!busy) s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
-      if (s->stop && s->queue.empty() && s->active.empty() && !busy) break;
-    }
-    if (!busy) {  // nothing runs to overlap with: free, then admit
-      free_retired(s);
-      (void)admit_queued(s);
+      if (!busy) s->cv_work.wait(lk, [&] { return s->stop || !s->active.empty() || s->want_free; });
+      if (s->stop && s->queue.empty() && s->active.empty() && !busy) break;  // the admission thread retires what it still sets up
     }
     // round k+1 is enqueued before round k is waited for, so that the device has the next round
-    // queued while the host collects results and admits requests
+    // queued while the host collects results
     Round& r = s->rounds[s->rounds[0].inflight ? 1 : 0];
     Round& other = s->rounds[&r == &s->rounds[0] ? 1 : 0];
     enqueue_round(s, r);
-    const bool want_free = admit_queued(s);
     Round* wait = nullptr;
     if (r.inflight && other.inflight) wait = other.id < r.id ? &other : &r;
     else if (!r.inflight && other.inflight) wait = &other;
@@ -527,15 +561,12 @@ void scheduler(nmfa_server* s) {
         (void)complete_round(s, o);
       }
     }
-    size_t n_retired;
+    bool free_now;
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      n_retired = s->retired.size();
+      free_now = s->want_free || s->retired.size() >= kRetireBatch;
     }
-    if (want_free || n_retired >= kRetireBatch) {
-      free_retired(s);
-      if (want_free) (void)admit_queued(s);
-    }
+    if (free_now) free_retired(s);
   }
   free_retired(s);
 }
@@ -590,6 +621,7 @@ extern "C" int nmfa_server_create(const nmfa_server_params* p, nmfa_server** out
     return nmfa_fail(NMFA_EDEVICE, "nmfa_server_create: event creation failed");
   }
   s->worker = std::thread(scheduler, s);
+  s->admitter = std::thread(admitter, s);
   *out = s;
   return NMFA_OK;
 }
@@ -626,7 +658,7 @@ extern "C" int nmfa_server_submit(nmfa_server* s, int32_t n, const double* J, co
     ++s->st.submitted;
     *ticket = j->id;
   }
-  s->cv_work.notify_one();
+  s->cv_admit.notify_one();
   return NMFA_OK;
 }
 
@@ -730,7 +762,11 @@ extern "C" void nmfa_server_destroy(nmfa_server* s) {
     for (Job* j : s->active) j->cancel = true;
   }
   s->cv_work.notify_all();
+  s->cv_admit.notify_all();
+  if (s->admitter.joinable()) s->admitter.join();
+  s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  free_retired(s);  // set-ups that ended after the scheduler
   for (auto& kv : s->jobs) {
     if (kv.second->ctx) nmfa_destroy(kv.second->ctx);
     if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
