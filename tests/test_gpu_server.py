@@ -107,8 +107,8 @@ def test_cancel_queued_and_running(nmfa):
 
 
 def test_large_jobs_side_by_side(nmfa):
-    # dense group-kernel jobs (one stream), sparse jobs (two streams) and small batched jobs in the
-    # same rounds: each result is the one the job gets alone, bit for bit
+    # dense group-kernel jobs, sparse jobs and small batched jobs in the same rounds, on four
+    # streams: each result is the one the job gets alone, bit for bit
     specs = [("sk", 500, 96, 400), ("sk", 900, 128, 300), ("sk", 1300, 64, 350),
              ("reg", 600, 200, 380), ("reg", 1100, 64, 420), ("reg", 1500, 130, 300),
              ("sk", 120, 80, 300), ("reg", 200, 50, 360)]
