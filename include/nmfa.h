@@ -209,14 +209,18 @@ int nmfa_noise_values(uint64_t seed, int32_t t, int32_t r0, int32_t n_rep, int32
 const char *nmfa_last_error(void);
 
 /* ---- serving: continuous batching of annealing requests ---------------------------------------
- * A server owns one GPU stream and a scheduler thread. Requests (instance, R, t_f, seed) are
- * admitted in arrival order while the device memory they need fits in hbm_budget_bytes and fewer
- * than max_active are running; a request that does not fit waits (later requests do not overtake
- * it), one larger than the whole budget fails with NMFA_ENOMEM. Admitted requests are advanced in
- * rounds of chunk_iters iterations: every round runs one batched launch of the persistent small-N
- * kernel over the replica blocks of all admitted small-N requests, plus the large-N requests'
- * own kernels, so requests that arrive while others run join at the next round and their work
- * overlaps on the device. J and the spin state stay on the device between rounds. Because the
+ * A server owns four GPU streams, a scheduler thread and an admission thread. Requests
+ * (instance, R, t_f, seed) are admitted in arrival order while the device memory they need fits
+ * in hbm_budget_bytes and fewer than max_active are running; a request that does not fit waits
+ * (later requests do not overtake it), one larger than the whole budget fails with NMFA_ENOMEM.
+ * The admission thread does each admitted request's host-side set-up and upload while the device
+ * runs. Admitted requests are advanced in rounds of chunk_iters iterations: every round runs one
+ * batched launch of the persistent small-N kernel over the replica blocks of all admitted small-N
+ * requests, plus the large-N requests' own kernels side by side on the other streams, and the
+ * next round is enqueued before the previous one is waited for; requests that arrive while others
+ * run join at a following round. J and the spin state stay on the device between rounds. A
+ * finished request's device memory is freed in batches (or when admission needs it), so
+ * bytes_in_use can stay above the running requests' needs for a while. Because the
  * noise is counter-based and every request's arithmetic depends only on that request, a
  * request's result is bit-identical alone and in any mix. The scheduler runs the paper's
  * Algorithm 1 per request exactly as nmfa_anneal does (same kernels, same precision). */
@@ -233,7 +237,7 @@ typedef struct nmfa_server_params {
 typedef struct nmfa_server_stats {
   uint64_t submitted, completed, failed, cancelled;
   uint64_t queued, active;            /* at the time of the call */
-  uint64_t bytes_in_use, peak_bytes;  /* admitted device bytes (the budget's accounting) */
+  uint64_t bytes_in_use, peak_bytes;  /* admitted, not yet freed device bytes (the budget's accounting) */
   uint64_t rounds, batched_launches;
 } nmfa_server_stats;
 
