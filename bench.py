@@ -498,8 +498,8 @@ def main() -> int:
         result["extra"] = extra
 
     if not args.no_serving:
-        # The server runs in a child process without torch, as it would be deployed: in a process
-        # where torch has set up the GPU, the same burst measured 72 instead of 107 requests/s.
+        # The server runs in a process of its own, as it would be deployed, apart from the torch
+        # state and device memory of the legs above.
         cmd = [sys.executable, os.path.abspath(__file__), "--serving-child",
                "--serving-burst", str(args.serving_burst), "--serving-requests", str(args.serving_requests),
                "--serving-budget-gib", str(args.serving_budget_gib)]

@@ -209,7 +209,7 @@ int nmfa_noise_values(uint64_t seed, int32_t t, int32_t r0, int32_t n_rep, int32
 const char *nmfa_last_error(void);
 
 /* ---- serving: continuous batching of annealing requests ---------------------------------------
- * A server owns four GPU streams, a scheduler thread and an admission thread. Requests
+ * A server owns three GPU streams, a scheduler thread and an admission thread. Requests
  * (instance, R, t_f, seed) are admitted in arrival order while the device memory they need fits
  * in hbm_budget_bytes and fewer than max_active are running; a request that does not fit waits
  * (later requests do not overtake it), one larger than the whole budget fails with NMFA_ENOMEM.

@@ -1,15 +1,17 @@
 // Continuous-batching annealing server (nmfa_server_* in include/nmfa.h).
 //
-// A scheduler thread owns four HIP streams; an admission thread takes requests from a FIFO queue
+// A scheduler thread owns three HIP streams (with the null stream, which the uploads use, that is
+// HIP's default of four hardware queues per process); an admission thread takes requests from a
+// FIFO queue
 // by device memory budget and a cap on concurrently admitted requests, and does their host-side
 // set-up and upload beside the running rounds. Admitted requests advance in rounds of
 // chunk_iters iterations of Algorithm 1:
 //   * all admitted requests on the persistent small-N path share ONE launch per round
 //     (anneal_small_batched over every request's replica blocks; each workgroup reads its own
-//     request's arguments);
-//   * larger requests advance by the same chunk on their own kernels in the same round, on the
-//     other three streams, so that their kernels run side by side with the batched launch and
-//     with each other. The workgroups of one persistent XCD-group launch wait for each other, so
+//     request's arguments), on the third stream;
+//   * larger requests advance by the same chunk on their own kernels in the same round, over the
+//     three streams, so that their kernels run side by side with the batched launch and with
+//     each other. The workgroups of one persistent XCD-group launch wait for each other, so
 //     group launches run side by side only where all of them fit on the chip at once: each of
 //     the three streams has a workgroup budget (half, a quarter and a quarter of the CUs, in
 //     multiples of the XCD count), each group launch on a stream is capped at that stream's
@@ -90,7 +92,7 @@ size_t job_bytes(int n, int R, int t_f, bool j_integral) {
 
 }  // namespace
 
-constexpr int SERVER_LANES = 3;  // streams besides the batched launch's (4 hardware queues in all)
+constexpr int SERVER_LANES = 3;  // kernel streams (with the null stream: 4 hardware queues in all)
 
 // One round of the pipeline: the chunk of every request advanced in it, and what the host keeps
 // until the round's work is complete (the batched launch's staging).
@@ -120,7 +122,7 @@ struct Retired {
 struct nmfa_server {
   nmfa_server_params p{};
   int device = 0;
-  hipStream_t stream = nullptr;            // the batched small-N launch
+  hipStream_t stream = nullptr;            // the batched small-N launch: the last lane
   hipStream_t lanes[SERVER_LANES] = {};    // group kernels on all three; sparse, per-iteration on [1..]
   int cus = 256;                           // compute units of the device
   std::mutex mu;
@@ -586,7 +588,6 @@ static void destroy_server_resources(nmfa_server* s) {
   if (s->ev_wide) (void)hipEventDestroy(s->ev_wide);
   for (hipStream_t ls : s->lanes)
     if (ls) (void)hipStreamDestroy(ls);
-  if (s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
 }
 
@@ -602,10 +603,13 @@ extern "C" int nmfa_server_create(const nmfa_server_params* p, nmfa_server** out
     return nmfa_fail(NMFA_EINVAL, "nmfa_server_create: invalid parameters");
   nmfa_server* s = new nmfa_server();
   s->p = *p;
-  // non-blocking streams: uploads of newly admitted requests (null stream) overlap the running round
-  bool ok = hipGetDevice(&s->device) == hipSuccess &&
-            hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+  // Non-blocking streams, so that uploads of newly admitted requests (null stream) overlap the
+  // running rounds. Three of them: with the null stream that is HIP's default of four hardware
+  // queues per process, so that no copy waits behind a kernel that merely shares its queue. The
+  // batched small-N launch shares the last lane.
+  bool ok = hipGetDevice(&s->device) == hipSuccess;
   for (hipStream_t& ls : s->lanes) ok = ok && hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) == hipSuccess;
+  s->stream = s->lanes[SERVER_LANES - 1];
   if (!ok) {
     destroy_server_resources(s);
     return nmfa_fail(NMFA_EDEVICE, "nmfa_server_create: no HIP device / stream");
