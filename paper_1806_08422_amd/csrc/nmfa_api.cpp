@@ -792,14 +792,15 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     // A new run clears the whole control block; a continued one (and every launch after the
     // first) only the registration and barrier counters, so that an abort in an earlier chunk of
     // the run stays raised, ends the later ones at once, and is reported when the run is read.
-    if (t_begin == 1) HIP_TRY(hipMemsetAsync(c->d_ctl, 0, (size_t)xcd_ctl_words() * 4, st));
+    const size_t ctl_words = (size_t)xcd_ctl_words();
+    uint32_t* ctl = reinterpret_cast<uint32_t*>(c->d_ctl);
+    if (t_begin == 1) HIP_TRY(launch_zero_words(ctl, 0, ctl_words, 0, 0, st));
     HIP_TRY(hipEventRecord(c->ev0, st));
     c->launches = 0;
     for (int gb = 0; gb < G; gb += per_launch) {
       const int ng = std::min(per_launch, G - gb);
       if (gb > 0 || t_begin > 1) {  // fresh registration and barrier counters; abort and mode persist
-        HIP_TRY(hipMemsetAsync(c->d_ctl, 0, 17 * 4, st));
-        HIP_TRY(hipMemsetAsync(c->d_ctl + 64, 0, (size_t)(xcd_ctl_words() - 64) * 4, st));
+        HIP_TRY(launch_zero_words(ctl, 0, 17, 64, ctl_words, st));
       }
       XcdArgs x{};
       x.S[0] = c->d_S[0];
@@ -818,7 +819,9 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     HIP_TRY(hipEventRecord(c->evm, st));
     c->ctl_pending = true;
   } else {
-    if (t_begin == 1) HIP_TRY(hipMemsetAsync(c->d_state, 0, (size_t)R * c->n * c->acc_size(), st));
+    if (t_begin == 1)
+      HIP_TRY(launch_zero_words(reinterpret_cast<uint32_t*>(c->d_state), 0, (size_t)R * c->n * c->acc_size() / 4, 0, 0,
+                                st));
     HIP_TRY(launch_pack_state(c->prec, c->d_state, c->d_S[0], c->n, R, c->Kp, c->Kp, a.Rp, t_begin == 1 ? 1 : 0, st));
     HIP_TRY(hipEventRecord(c->ev0, st));
     int cur = 0;

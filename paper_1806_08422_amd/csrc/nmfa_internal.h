@@ -56,6 +56,8 @@ size_t xcd_chunk_bytes();
 int xcd_spin_stride(int Kp);  // row stride of S for the XCD kernel
 int xcd_pick_buffers(size_t lds_room);  // chunk buffers that fit in lds_room bytes (0 if < 2)
 int xcd_ctl_words();
+// Zero words [a0, a1) and [b0, b1) of p (device) on st; either range may be empty.
+hipError_t launch_zero_words(uint32_t* p, size_t a0, size_t a1, size_t b0, size_t b1, hipStream_t st);
 int xcd_rows();
 int xcd_group_replicas();
 size_t small_lds_bytes(int prec, int Mp, int stride);
