@@ -120,6 +120,10 @@ int nmfa_create(int32_t n, const double *J, const double *h, const nmfa_params *
  * and the energies of all R samples, enqueued on `hip_stream` (a hipStream_t; NULL = the null
  * stream). Asynchronous: returns after enqueueing; results are read with nmfa_spins /
  * nmfa_energies, which synchronise. Device buffers are (re)allocated only when R grows.
+ * A call may be recorded into a HIP graph on a capturing stream once an earlier call with the
+ * same R and t_f has run eagerly (that call allocates the run buffers and uploads the schedule;
+ * a recorded call enqueues kernels and event records only); replaying the graph repeats the
+ * recorded call exactly, seed included.
  * Errors: EINVAL (R < 1, t_f < 1), ENOMEM, EDEVICE. */
 int nmfa_anneal(nmfa_ctx *c, int32_t R, int32_t t_f, uint64_t seed, void *hip_stream);
 
