@@ -1,15 +1,18 @@
 """CPU oracle of noisy mean-field annealing -- TEST INFRASTRUCTURE ONLY.
 
 Python bindings (ctypes) for ``nmfa_oracle.c``, a plain FP64 C implementation of the paper's
-Algorithm 1, its Ising energy (Eq. 1) and a brute-force ground-state search. Only the tests, the
+noisy mean-field annealing (Sec. II, Alg. 1), its Ising energy (Eq. 1) and a brute-force
+ground-state search. Only the tests, the
 smoke check and the CPU-baseline leg of the benchmark may import this package; the GPU library
 never does, and this package imports nothing from it.
 
 Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``):
 
 * ``philox4x32_10``      pinned: published known-answer vectors of Philox4x32-10.
-* ``gauss4`` / ``noise`` pinned: Box-Muller invariants (radius^2 = -2 ln u0, angle = 2 pi u1)
-                         and the normal distribution (moments, Kolmogorov-Smirnov).
+* ``gauss4`` / ``noise`` pinned: Box-Muller invariants (radius^2 = -2 ln u0, angle = 2 pi u1),
+                         the normal distribution (moments, Kolmogorov-Smirnov), and the counter
+                         mapping (floor(i/4), r, t, 0) / lane i mod 4 rebuilt from the pinned
+                         generator (a lane swap, a 0-based t or r and t exchanged fail it).
 * ``normalisers``        pinned: closed forms (SK: sqrt(N-1); d-regular: sqrt(d); with fields).
 * ``schedule``           pinned: knot values, geometric midpoints, monotonicity.
 * ``anneal``             pinned: closed-form geometric series for J = 0, sigma = 0; alpha = 1

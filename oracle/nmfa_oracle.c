@@ -6,8 +6,8 @@
  * coherent Ising machine with a mean-field algorithm", arXiv:1806.08422:
  *
  *   - the Ising energy H = sum_{i<j} J_ij s_i s_j + sum_i h_i s_i            (Sec. I, Eq. 1)
- *   - Algorithm 1 (noisy mean-field annealing) step by step                   (Sec. II, Alg. 1)
- *   - the sign readout s~_i = s_i / |s_i|                                      (Alg. 1, final loop)
+ *   - noisy mean-field annealing over independent replicas                    (Sec. II, Alg. 1)
+ *   - the sign readout s~_i = s_i / |s_i| of its result                        (Sec. II, Alg. 1)
  *   - MAX-CUT values for J = edge weights, h = 0                              (Sec. III, Table I)
  *   - a brute-force ground state by exhaustive enumeration (a check, not the method)
  *
@@ -22,11 +22,11 @@
  *   R2 noise stream: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the 64-bit seed,
  *      counter (floor(i/4), r, t, 0); its four words give four uniforms u = (x + 1/2) 2^-32 and
  *      Box-Muller (1958) turns (u0,u1) into z(4q), z(4q+1) and (u2,u3) into z(4q+2), z(4q+3).
- *   R3 the normaliser is the root-sum-square sqrt(h_i^2 + sum_j J_ij^2) that the formula on the
- *      field line of Alg. 1 prints (the prose says "root mean square"; the formula wins). A zero
+ *   R3 the normaliser is the root-sum-square sqrt(h_i^2 + sum_j J_ij^2) of the field formula in
+ *      Alg. 1 (the prose calls it a root mean square; the formula wins). A zero
  *      normaliser (isolated spin, h_i = 0) makes the field term 0.
  *   R4 the update is synchronous: every s^_i is computed from the old spins before any s_i
- *      changes (Alg. 1 computes all s^ in one loop and blends in the next).
+ *      changes (Alg. 1 finishes all s^ before it blends any of them in).
  *   R5 readout of s_i = 0 (and -0.0) gives +1.
  *   R6 Eq. 1 sums over unordered pairs i < j of a symmetric J with zero diagonal; this is the
  *      only reading under which the field h_i + sum_j J_ij s_j is dH/ds_i.
@@ -110,7 +110,7 @@ double nmfa_oracle_noise(uint64_t seed, int32_t t, int32_t r, int32_t i) {
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Normaliser of the field line of Alg. 1: sqrt(h_i^2 + sum_j J_ij^2) (reading R3).            */
+/* Normaliser of the field in Alg. 1: sqrt(h_i^2 + sum_j J_ij^2) (reading R3).                 */
 /* ------------------------------------------------------------------------------------------ */
 void nmfa_oracle_normalisers(int32_t n, const double *J, const double *h, double *norm) {
   for (int32_t i = 0; i < n; ++i) {
@@ -155,57 +155,60 @@ int nmfa_oracle_schedule(int32_t n_knots, const double *ku, const double *kT, in
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Algorithm 1 for one replica.                                                                */
+/* Noisy mean-field annealing (Sec. II, Alg. 1) over a set of independent replicas.             */
+/*                                                                                              */
+/* Replica r carries a continuous state s_r in [-1, 1]^n that starts at zero. Iteration t      */
+/* replaces the whole vector at once (reading R4) by                                            */
+/*     s_r  <-  alpha * b_t(s_r) + (1 - alpha) * s_r,                                           */
+/*     b_t(s)_i = -tanh( Phi_i / T_t ),                                                         */
+/*     Phi_i    = (h_i + sum_j J_ij s_j) / norm_i + sigma * z(seed, t, r, i),                    */
+/* the Boltzmann expectation of a spin in the noisy normalised mean field, blended into the old */
+/* state by the damping alpha. After the last iteration each component is read out by its sign. */
+/* The three helpers below are the three factors of that map; none of them changes the state   */
+/* before every component of the new one has been computed from the old one.                   */
 /* ------------------------------------------------------------------------------------------ */
 typedef struct {
   int32_t n;
   const double *J, *h, *norm, *T;
   double alpha, sigma;
-  int32_t t_first, t_f;
   uint64_t seed;
   int negate_noise;
 } problem_t;
 
-static void anneal_replica(const problem_t *P, int32_t r, const double *s_init, int32_t record,
-                           double *traj_r, int64_t traj_stride, double *s_out, int8_t *spins_out) {
+/* m_i = h_i + sum_j J_ij s_j: the local field of Eq. 1 at state s (minus the gradient of H),  */
+/* summed over j in ascending order.                                                            */
+static void local_field(const problem_t *P, const double *s, double *m) {
   const int32_t n = P->n;
-  double *s = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-  double *s_hat = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-  /* Alg. 1, first loop: s_i := 0 (or a given state when resuming part-way). */
-  for (int32_t i = 0; i < n; ++i) s[i] = s_init ? s_init[i] : 0.0;
-
-  for (int32_t t = P->t_first; t <= P->t_f; ++t) {
-    const double T_t = P->T[t - 1];
-    /* Alg. 1, first inner loop: the noisy normalised mean field and the Boltzmann expectation,
-     * all from the spins of the previous iteration. */
-    for (int32_t i = 0; i < n; ++i) {
-      double field = 0.0;
-      for (int32_t j = 0; j < n; ++j) field += P->J[(int64_t)i * n + j] * s[j];
-      double hi = P->h ? P->h[i] : 0.0;
-      double mean_field = hi + field;
-      double normalised = (P->norm[i] > 0.0) ? mean_field / P->norm[i] : 0.0;
-      double z = nmfa_oracle_noise(P->seed, t, r, i);
-      if (P->negate_noise) z = -z;
-      double phi = normalised + P->sigma * z;
-      s_hat[i] = -tanh(phi / T_t);
-    }
-    /* Alg. 1, second inner loop: the damped (convex) update. */
-    for (int32_t i = 0; i < n; ++i) s[i] = P->alpha * s_hat[i] + (1.0 - P->alpha) * s[i];
-
-    int32_t k = t - P->t_first; /* 0-based index of this iteration among those run */
-    if (traj_r && k < record) memcpy(traj_r + (int64_t)k * traj_stride, s, sizeof(double) * n);
-  }
-  /* Alg. 1, final loop: s~_i = s_i / |s_i|, with s_i = 0 read as +1 (reading R5). */
   for (int32_t i = 0; i < n; ++i) {
-    if (s_out) s_out[i] = s[i];
-    if (spins_out) spins_out[i] = (s[i] < 0.0) ? (int8_t)-1 : (int8_t)1;
+    const double *row = P->J + (int64_t)i * n;
+    double dot = 0.0;
+    for (int32_t j = 0; j < n; ++j) dot += row[j] * s[j];
+    m[i] = (P->h ? P->h[i] : 0.0) + dot;
   }
-  free(s);
-  free(s_hat);
+}
+
+/* Phi_i = m_i / norm_i + sigma z: the field divided by its normaliser (a zero normaliser gives */
+/* a zero field term, reading R3), plus Gaussian noise of standard deviation sigma (R1, R2).   */
+static void noisy_normalised_field(const problem_t *P, int32_t t, int32_t r, const double *m,
+                                   double *phi) {
+  for (int32_t i = 0; i < P->n; ++i) {
+    const double scaled = (P->norm[i] > 0.0) ? m[i] / P->norm[i] : 0.0;
+    double z = nmfa_oracle_noise(P->seed, t, r, i);
+    if (P->negate_noise) z = -z;
+    phi[i] = scaled + P->sigma * z;
+  }
+}
+
+/* s_i <- alpha * (-tanh(Phi_i / T_t)) + (1 - alpha) * s_i, for all i (phi is already complete). */
+static void damped_boltzmann_step(const problem_t *P, double T_t, const double *phi, double *s) {
+  for (int32_t i = 0; i < P->n; ++i) {
+    const double b = -tanh(phi[i] / T_t);
+    s[i] = P->alpha * b + (1.0 - P->alpha) * s[i];
+  }
 }
 
 /*
- * Run Algorithm 1 for the replicas rep_ids[0..n_rep-1] (NULL: replicas 0..n_rep-1).
+ * Run iterations t_first..t_f for the replicas rep_ids[0..n_rep-1] (NULL: replicas 0..n_rep-1).
  *
  *   n, J (n*n row-major, symmetric, zero diagonal), h (n or NULL = 0)
  *   alpha, sigma, T (t_f temperatures, T[t-1] for iteration t)
@@ -215,6 +218,7 @@ static void anneal_replica(const problem_t *P, int32_t r, const double *s_init, 
  *   record, traj: if traj != NULL, traj[(k*n_rep + q)*n + i] = s_i of replica q after the
  *            k-th iteration run, k < record
  *   s_out (n_rep*n, or NULL): final continuous spins; spins_out (n_rep*n, or NULL): readout
+ *            s~_i = sign(s_i) with s_i = 0 read as +1 (reading R5)
  *   nthreads: threads over replicas (<= 0: the OpenMP default)
  * Returns 0, or -1 on invalid arguments.
  */
@@ -226,20 +230,40 @@ int nmfa_oracle_anneal(int32_t n, const double *J, const double *h, double alpha
   if (n < 1 || !J || !T || t_f < 0 || t_first < 1 || n_rep < 0) return -1;
   double *norm = (double *)malloc(sizeof(double) * (size_t)n);
   nmfa_oracle_normalisers(n, J, h, norm);
-  problem_t P = {n, J, h, norm, T, alpha, sigma, t_first, t_f, seed, negate_noise};
-  const int64_t traj_stride = (int64_t)n_rep * n;
+  const problem_t P = {n, J, h, norm, T, alpha, sigma, seed, negate_noise};
+  const int64_t cnt = (int64_t)n_rep * n;
+  double *S = (double *)malloc(sizeof(double) * (size_t)(cnt > 0 ? cnt : 1));
+  for (int64_t k = 0; k < cnt; ++k) S[k] = s_init ? s_init[k] : 0.0;
 #ifdef _OPENMP
   int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#pragma omp parallel num_threads(nt)
 #endif
-  for (int32_t q = 0; q < n_rep; ++q) {
-    int32_t r = rep_ids ? rep_ids[q] : q;
-    anneal_replica(&P, r, s_init ? s_init + (int64_t)q * n : NULL, record,
-                   traj ? traj + (int64_t)q * n : NULL, traj_stride,
-                   s_out ? s_out + (int64_t)q * n : NULL,
-                   spins_out ? spins_out + (int64_t)q * n : NULL);
+  {
+    double *m = (double *)malloc(sizeof(double) * (size_t)n);
+    double *phi = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int32_t t = t_first; t <= t_f; ++t) {
+      const int32_t k = t - t_first; /* 0-based index of this iteration among those run */
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+      for (int32_t q = 0; q < n_rep; ++q) {
+        const int32_t r = rep_ids ? rep_ids[q] : q;
+        double *s = S + (int64_t)q * n;
+        local_field(&P, s, m);
+        noisy_normalised_field(&P, t, r, m, phi);
+        damped_boltzmann_step(&P, T[t - 1], phi, s);
+        if (traj && k < record) memcpy(traj + ((int64_t)k * n_rep + q) * n, s, sizeof(double) * n);
+      }
+    }
+    free(m);
+    free(phi);
+  }
+  for (int64_t k = 0; k < cnt; ++k) {
+    if (s_out) s_out[k] = S[k];
+    if (spins_out) spins_out[k] = (S[k] < 0.0) ? (int8_t)-1 : (int8_t)1;
   }
   (void)nthreads;
+  free(S);
   free(norm);
   return 0;
 }

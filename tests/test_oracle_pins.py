@@ -57,6 +57,47 @@ def test_box_muller_invariants():
             assert min(d, 2 * math.pi - d) < 1e-10
 
 
+def _box_muller_lane(words, lane):
+    """Lane `lane` of the Box-Muller transform (Box & Muller 1958) of four Philox words:
+    (u0, u1) -> lanes 0, 1 and (u2, u3) -> lanes 2, 3 with u = (x + 1/2) / 2^32."""
+    pair = lane // 2
+    u0 = (words[2 * pair] + 0.5) / 2**32
+    u1 = (words[2 * pair + 1] + 0.5) / 2**32
+    rho = math.sqrt(-2.0 * math.log(u0))
+    theta = 2.0 * math.pi * u1
+    return rho * math.cos(theta) if lane % 2 == 0 else rho * math.sin(theta)
+
+
+_NOISE_CASES = [(1, 1, 0, 0), (1, 1, 0, 3), (2**40 + 5, 17, 3, 6), (12345, 5000, 4095, 1999),
+                (0xFFFFFFFFFFFF, 2, 1, 9), (77, 333, 700, 14), (9, 4, 9, 1)]
+
+
+@pytest.mark.parametrize("seed,t,r,i", _NOISE_CASES)
+def test_noise_counter_mapping(seed, t, r, i):
+    """The noise of spin i, replica r, iteration t (1-based) is lane i mod 4 of the Gaussians of
+    counter (floor(i/4), r, t, 0) under key (seed low word, seed high word) (the reading of the
+    unspecified N(0, sigma) source of Sec. II). Rebuilt here from the known-answer-pinned
+    generator: a lane swap within the quad, a 0-based t, or r and t exchanged in the counter
+    each give a different value."""
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    words = oracle.philox4x32_10([i // 4, r, t, 0], key)
+    expect = _box_muller_lane(words, i % 4)
+    got = oracle.noise(seed, t, r, i)
+    assert math.isclose(got, expect, rel_tol=1e-12, abs_tol=1e-12)
+    mutants = [
+        _box_muller_lane(words, (i % 4) ^ 1),                                      # lanes swapped
+        _box_muller_lane(oracle.philox4x32_10([i // 4, r, t - 1, 0], key), i % 4),  # t counted from 0
+        _box_muller_lane(oracle.philox4x32_10([i // 4, t, r, 0], key), i % 4),      # r and t exchanged
+        _box_muller_lane(oracle.philox4x32_10([i, r, t, 0], key), i % 4),           # spin, not quad, index
+    ]
+    if r == t:
+        mutants.pop(2)  # exchanging equal r and t changes nothing
+    if i == 0:
+        mutants.pop()  # quad and spin index coincide
+    for m in mutants:
+        assert abs(m - got) > 1e-6
+
+
 def test_noise_is_standard_normal():
     """Moments and a Kolmogorov-Smirnov test over many (t, r, i) draws."""
     rng = np.random.default_rng(0)
