@@ -1,20 +1,19 @@
 /*
  * nmfa.h -- C ABI of the MI355X (gfx950) noisy mean-field annealing library (libnmfa.so).
  *
- * Noisy mean-field annealing (NMFA) is Algorithm 1 of A. D. King, W. Bernoudy, J. King,
+ * Noisy mean-field annealing (NMFA) is the method of A. D. King, W. Bernoudy, J. King,
  * A. J. Berkley, T. Lanting, "Emulating the coherent Ising machine with a mean-field algorithm"
- * (arXiv:1806.08422, Sec. II). Given an Ising problem (h, J) and parameters T (a decreasing
- * temperature schedule), sigma and alpha it produces samples s~ in {-1,+1}^N; this library runs
- * R independent samples ("replicas") at once on one GPU:
+ * (arXiv:1806.08422, Sec. II, Alg. 1). For an Ising problem (h, J) it anneals a continuous state
+ * s in [-1, 1]^N from s = 0 over t = 1..t_f iterations of a decreasing temperature T_t. One
+ * iteration replaces every component at once by a damped Boltzmann expectation in the noisy,
+ * normalised mean field:
  *
- *   s_i := 0
- *   for t = 1..t_f:
- *     Phi_i := (h_i + sum_j J_ij s_j) / sqrt(h_i^2 + sum_j J_ij^2) + N(0, sigma)   for all i
- *     s^_i  := -tanh(Phi_i / T_t)                                                 for all i
- *     s_i   := alpha s^_i + (1 - alpha) s_i                                        for all i
- *   s~_i := s_i / |s_i|
+ *   s_i <- alpha * ( -tanh( [ (h_i + (J s)_i) / sqrt(h_i^2 + sum_j J_ij^2) + sigma z_i ] / T_t ) )
+ *          + (1 - alpha) * s_i,            z_i ~ N(0, 1) independently for every (t, replica, i),
  *
- * and evaluates the Ising energy of Eq. 1, H = sum_{i<j} J_ij s~_i s~_j + sum_i h_i s~_i.
+ * and the sample is the sign of the final state. This library runs R independent samples
+ * ("replicas") at once on one GPU and evaluates the Ising energy of Eq. 1,
+ * H = sum_{i<j} J_ij s_i s_j + sum_i h_i s_i, of each sample.
  *
  * Conventions shared by every entry point:
  *   - Every call returns an int status: NMFA_OK (0) or a negative NMFA_E* code. A failing call
@@ -30,7 +29,8 @@
  *   - Temperature schedule (the paper's Fig. 2 is a three-segment piecewise-exponential
  *     schedule whose values are not printed): knots (u_k, T_k), u_0 = 0 < ... < u_K = 1, log T
  *     linear between knots, T_t = T((t-1)/(t_f-1)). The default knots are
- *     (0, 10) (0.1, 2) (0.6, 0.5) (1, 0.05).
+ *     (0, 10) (0.1, 2) (0.6, 0.5) (1, 0.05). A caller may instead pass the temperatures
+ *     T_1..T_tf themselves (nmfa_params.T_explicit).
  */
 #ifndef NMFA_H
 #define NMFA_H
@@ -97,11 +97,17 @@ typedef struct nmfa_params {
   const double *knot_T;    /* n_knots temperatures > 0 */
   uint32_t flags;          /* NMFA_FLAG_* */
   int32_t record_iters;    /* keep s after each of the first record_iters iterations */
+  int32_t n_T_explicit;    /* 0: temperatures from the knots. Else the schedule is given point by
+                              point: T_t = T_explicit[t-1] for t = 1..n_T_explicit (the knots are
+                              ignored), and every anneal of the context must use t_f = n_T_explicit
+                              (others fail with NMFA_EINVAL) */
+  const double *T_explicit; /* n_T_explicit finite temperatures > 0 (host; copied at create) */
 } nmfa_params;
 
 typedef struct nmfa_ctx nmfa_ctx;
 
-/* Defaults: alpha = sigma = 0.15, default schedule, NMFA_BF16, no flags, no recording. */
+/* Defaults: alpha = sigma = 0.15, default schedule (no explicit temperatures), NMFA_BF16, no
+ * flags, no recording. */
 void nmfa_params_default(nmfa_params *p);
 
 /* Create a solver for the instance (h, J) (Eq. 1; Alg. 1 inputs).
@@ -124,7 +130,8 @@ int nmfa_create(int32_t n, const double *J, const double *h, const nmfa_params *
  * same R and t_f has run eagerly (that call allocates the run buffers and uploads the schedule;
  * a recorded call enqueues kernels and event records only); replaying the graph repeats the
  * recorded call exactly, seed included.
- * Errors: EINVAL (R < 1, t_f < 1), ENOMEM, EDEVICE. */
+ * Errors: EINVAL (R < 1, t_f < 1, t_f other than n_T_explicit when explicit temperatures
+ * were given), ENOMEM, EDEVICE. */
 int nmfa_anneal(nmfa_ctx *c, int32_t R, int32_t t_f, uint64_t seed, void *hip_stream);
 
 /* Checkpoint/resume form: run iterations t_begin..t_end (1 <= t_begin <= t_end <= t_f) of a
@@ -139,8 +146,11 @@ int nmfa_anneal_range(nmfa_ctx *c, int32_t R, int32_t t_f, int32_t t_begin, int3
 int nmfa_spins(nmfa_ctx *c, int8_t *out, int32_t on_device);
 
 /* Copy the R energies H(s~) (Eq. 1 over pairs i<j) to E (host, R doubles). If J and h are
- * integral, E_int (host, R int64, or NULL) receives the exact integer energies; otherwise
- * E_int is filled with 0. Synchronises. Errors: ESTATE, EDEVICE. */
+ * integral (and max|J_ij| * n^2 < 2^52, so that every partial sum is exact), E_int (host, R int64,
+ * or NULL) receives the exact integer energies; otherwise E_int is filled with 0. Synchronises.
+ * On the group-kernel paths (2-5) every call that reads results or state also checks the kernels'
+ * abort word, also after a run replayed from a recorded HIP graph. Errors: ESTATE, EDEVICE (a HIP
+ * call failed, or a group barrier of the run timed out). */
 int nmfa_energies(nmfa_ctx *c, double *E, int64_t *E_int);
 
 /* MAX-CUT values (Table I convention, J = edge weights, h = 0): cut_r = (sum_{i<j} J_ij - H_r)/2.
@@ -195,6 +205,12 @@ int nmfa_j_format(nmfa_ctx *c, int32_t *fmt);
  * kernel launches (1 for the persistent kernels, one per iteration for the per-iteration path).
  * Any output pointer may be NULL. Synchronises. Errors: ESTATE, EDEVICE. */
 int nmfa_last_timing(nmfa_ctx *c, double *anneal_ms, double *total_ms, int32_t *launches);
+
+/* Test hook for the group-kernel paths (2-5): sets the kernels' abort word as a group barrier
+ * that timed out would, so that a caller can check that the next read of results or state
+ * reports NMFA_EDEVICE. nmfa_set_state and the next anneal from t = 1 clear it.
+ * Errors: EINVAL (not a group-kernel context), EDEVICE. */
+int nmfa_debug_raise_abort(nmfa_ctx *c);
 
 /* Release every device and host resource of the context (NULL is ignored). */
 void nmfa_destroy(nmfa_ctx *c);

@@ -260,6 +260,11 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return fail(NMFA_EINVAL, "nmfa_create: alpha must be in (0, 1]");
   if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return fail(NMFA_EINVAL, "nmfa_create: sigma must be >= 0");
   if (p->record_iters < 0) return fail(NMFA_EINVAL, "nmfa_create: record_iters < 0");
+  if (p->n_T_explicit < 0 || (p->n_T_explicit > 0 && !p->T_explicit))
+    return fail(NMFA_EINVAL, "nmfa_create: invalid explicit temperatures");
+  for (int k = 0; k < p->n_T_explicit; ++k)
+    if (!(p->T_explicit[k] > 0.0) || !std::isfinite(p->T_explicit[k]))
+      return fail(NMFA_EINVAL, "nmfa_create: explicit temperature %d is not a finite value > 0", k);
 
   // schedule knots
   std::vector<double> ku, kT;
@@ -357,6 +362,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   c->record = p->record_iters;
   c->ku = ku;
   c->kT = kT;
+  if (p->n_T_explicit > 0) c->T_explicit.assign(p->T_explicit, p->T_explicit + p->n_T_explicit);
   (void)hipGetDevice(&c->device);
   bool any_h = false;
   if (h) {
@@ -375,6 +381,11 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     Jmax = std::max(Jmax, rows[i].jmax);
   }
   const bool use_J8 = c->J_integral && Jmax <= 127;
+  // integral couplings beyond the int8 range: the FP64 energy kernel's sums are exact integers as
+  // long as every |sum_i s_i sum_j J_ij s_j| stays below 2^53
+  const bool pairs_exact_f64 = c->J_integral && (double)Jmax * (double)n * (double)n < 4503599627370496.0;
+  c->exact_int = c->h_integral && (use_J8 || pairs_exact_f64);
+  c->pairs_exact_f64 = pairs_exact_f64 && !use_J8;
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j) c->w_total += Jf[(size_t)i * n + j];
 
@@ -653,6 +664,12 @@ static int ensure_run_buffers(nmfa_ctx* c, int R) {
   return NMFA_OK;
 }
 
+// Temperature of iteration t of a t_f-iteration run: the caller's own value when the context
+// holds explicit temperatures, else the knot schedule.
+static double ctx_T(const nmfa_ctx* c, int t, int t_f) {
+  return c->T_explicit.empty() ? schedule_T(c->ku, c->kT, t, t_f) : c->T_explicit[t - 1];
+}
+
 static int ensure_coef(nmfa_ctx* c, int t_f) {
   if (c->coef_tf == t_f && c->d_coef) return NMFA_OK;
   (void)hipFree(c->d_coef);
@@ -661,12 +678,12 @@ static int ensure_coef(nmfa_ctx* c, int t_f) {
   const double two_log2e = 2.0 / std::log(2.0);
   if (c->prec == NMFA_FP64) {
     std::vector<double> v(t_f);
-    for (int t = 1; t <= t_f; ++t) v[t - 1] = 1.0 / schedule_T(c->ku, c->kT, t, t_f);
+    for (int t = 1; t <= t_f; ++t) v[t - 1] = 1.0 / ctx_T(c, t, t_f);
     HIP_TRY(hipMalloc(&c->d_coef, (size_t)t_f * 8));
     HIP_TRY(hipMemcpy(c->d_coef, v.data(), (size_t)t_f * 8, hipMemcpyHostToDevice));
   } else {
     std::vector<float> v(t_f);
-    for (int t = 1; t <= t_f; ++t) v[t - 1] = (float)(two_log2e / schedule_T(c->ku, c->kT, t, t_f));
+    for (int t = 1; t <= t_f; ++t) v[t - 1] = (float)(two_log2e / ctx_T(c, t, t_f));
     HIP_TRY(hipMalloc(&c->d_coef, (size_t)t_f * 4));
     HIP_TRY(hipMemcpy(c->d_coef, v.data(), (size_t)t_f * 4, hipMemcpyHostToDevice));
   }
@@ -682,6 +699,9 @@ int ctx_prepare_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_
   if (t_f < 1) return fail(NMFA_EINVAL, "nmfa_anneal: t_f = %d < 1", t_f);
   if (t_begin < 1 || t_end < t_begin || t_end > t_f)
     return fail(NMFA_EINVAL, "nmfa_anneal: need 1 <= t_begin (%d) <= t_end (%d) <= t_f (%d)", t_begin, t_end, t_f);
+  if (!c->T_explicit.empty() && (size_t)t_f != c->T_explicit.size())
+    return fail(NMFA_EINVAL, "nmfa_anneal: t_f = %d but the context holds %zu explicit temperatures", t_f,
+                c->T_explicit.size());
   if (t_begin > 1 && !(c->state_valid && c->R == R))
     return fail(NMFA_ESTATE, "nmfa_anneal: t_begin > 1 needs the state of a previous call with R = %d", R);
   HIP_TRY(hipSetDevice(c->device));
@@ -741,7 +761,8 @@ int ctx_finish_run(nmfa_ctx* c, hipStream_t st) {
     HIP_TRY(launch_energy_i8(c->d_J8, c->Np8, c->d_h, c->h_integral ? 1 : 0, c->d_spins, c->n, c->R, c->d_Sp,
                              c->d_E2, c->d_Eint, c->d_E, st));
   else
-    HIP_TRY(launch_energy(nullptr, c->d_J64, c->d_h, 0, c->d_spins, c->n, c->R, c->d_Eint, c->d_E, st));
+    HIP_TRY(launch_energy(nullptr, c->d_J64, c->d_h, c->exact_int ? 1 : 0, c->d_spins, c->n, c->R, c->d_Eint, c->d_E,
+                          st));
   HIP_TRY(hipEventRecord(c->ev1, st));
   c->timed = true;
   c->state_valid = true;
@@ -854,18 +875,27 @@ static int sync_ctx(nmfa_ctx* c) {
 }
 
 // After the work of a run has completed: the XCD-group kernels' abort and exchange-mode words.
+// They are read on every access to results or state, not only after an anneal enqueued through
+// this library, so that a run replayed from a recorded HIP graph is checked as well.
 static int check_ctl(nmfa_ctx* c) {
-  if (c->ctl_pending) {
-    unsigned flags[3] = {0, 0, 0};
-    HIP_TRY(hipMemcpy(flags, c->d_ctl + 16, sizeof(flags), hipMemcpyDeviceToHost));
-    c->ctl_pending = false;
-    c->exchange_mode = (int)flags[2];
-    if (flags[1]) {
-      c->result_valid = false;
-      c->state_valid = false;
-      return fail(NMFA_EDEVICE, "XCD-group kernel: a group barrier or the start-up registration timed out");
-    }
+  if (c->path != 2 || !c->d_ctl) return NMFA_OK;
+  unsigned flags[3] = {0, 0, 0};
+  HIP_TRY(hipMemcpy(flags, c->d_ctl + 16, sizeof(flags), hipMemcpyDeviceToHost));
+  c->ctl_pending = false;
+  if (flags[2]) c->exchange_mode = (int)flags[2];
+  if (flags[1]) {
+    c->result_valid = false;
+    c->state_valid = false;
+    return fail(NMFA_EDEVICE, "XCD-group kernel: a group barrier or the start-up registration timed out");
   }
+  return NMFA_OK;
+}
+
+extern "C" int nmfa_debug_raise_abort(nmfa_ctx* c) {
+  if (!c || c->path != 2 || !c->d_ctl) return fail(NMFA_EINVAL, "nmfa_debug_raise_abort: not a group-kernel context");
+  HIP_TRY(hipSetDevice(c->device));
+  const unsigned one = 1u;
+  HIP_TRY(hipMemcpy(c->d_ctl + 17, &one, sizeof(one), hipMemcpyHostToDevice));
   return NMFA_OK;
 }
 
@@ -875,7 +905,7 @@ int ctx_read_results(nmfa_ctx* c, double* E, int64_t* E_int, int8_t* spins) {
   int rc = check_ctl(c);
   if (rc) return rc;
   HIP_TRY(hipMemcpy(E, c->d_E, (size_t)c->R * 8, hipMemcpyDeviceToHost));
-  if (c->J_integral && c->h_integral && c->d_J8)
+  if (c->exact_int)
     HIP_TRY(hipMemcpy(E_int, c->d_Eint, (size_t)c->R * 8, hipMemcpyDeviceToHost));
   else
     std::memset(E_int, 0, (size_t)c->R * 8);
@@ -900,7 +930,7 @@ extern "C" int nmfa_energies(nmfa_ctx* c, double* E, int64_t* E_int) {
   if (rc) return rc;
   HIP_TRY(hipMemcpy(E, c->d_E, (size_t)c->R * 8, hipMemcpyDeviceToHost));
   if (E_int) {
-    if (c->J_integral && c->h_integral && c->d_J8) {
+    if (c->exact_int) {
       HIP_TRY(hipMemcpy(E_int, c->d_Eint, (size_t)c->R * 8, hipMemcpyDeviceToHost));
     } else {
       std::memset(E_int, 0, (size_t)c->R * 8);
@@ -939,12 +969,12 @@ extern "C" int nmfa_energies_of(nmfa_ctx* c, int32_t R, const int8_t* spins, dou
     if (c->d_J8)
       e = launch_energy_i8(c->d_J8, c->Np8, c->d_h, c->h_integral ? 1 : 0, d_s, c->n, R, d_Sp, d_E2, d_Ei, d_E, 0);
     else
-      e = launch_energy(nullptr, c->d_J64, c->d_h, 0, d_s, c->n, R, d_Ei, d_E, 0);
+      e = launch_energy(nullptr, c->d_J64, c->d_h, c->exact_int ? 1 : 0, d_s, c->n, R, d_Ei, d_E, 0);
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(E, d_E, (size_t)R * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess && E_int) {
-    if (c->J_integral && c->h_integral && c->d_J8) e = hipMemcpy(E_int, d_Ei, (size_t)R * 8, hipMemcpyDeviceToHost);
+    if (c->exact_int) e = hipMemcpy(E_int, d_Ei, (size_t)R * 8, hipMemcpyDeviceToHost);
     else std::memset(E_int, 0, (size_t)R * 8);
   }
   (void)hipFree(d_s);
@@ -978,8 +1008,11 @@ extern "C" int nmfa_set_state(nmfa_ctx* c, int32_t R, const double* in) {
   for (size_t k = 0; k < cnt; ++k)
     if (!(std::fabs(in[k]) <= 1.0)) return fail(NMFA_EINVAL, "nmfa_set_state: state values must lie in [-1, 1]");
   HIP_TRY(hipSetDevice(c->device));
-  int rc = sync_ctx(c);
-  if (rc) return rc;
+  if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
+  else HIP_TRY(hipDeviceSynchronize());
+  // a new state replaces whatever an aborted group-kernel run left: clear its abort word
+  if (c->path == 2 && c->d_ctl) HIP_TRY(hipMemset(c->d_ctl + 17, 0, sizeof(unsigned)));
+  int rc;
   if ((rc = ensure_run_buffers(c, R)) != NMFA_OK) return rc;
   if (c->prec == NMFA_FP64) {
     HIP_TRY(hipMemcpy(c->d_state, in, cnt * 8, hipMemcpyHostToDevice));

@@ -26,9 +26,12 @@ struct nmfa_ctx {
   uint32_t flags = 0;
   int record = 0;
   std::vector<double> ku, kT;
+  std::vector<double> T_explicit;  // caller's temperatures T_1..T_tf (empty: the knots)
   std::vector<double> h;  // empty if h = 0
   bool has_h = false;
   bool J_integral = false, h_integral = true;
+  bool exact_int = false;        // energies are also returned as exact integers (J, h integral)
+  bool pairs_exact_f64 = false;  // integral J beyond int8: the FP64 energy kernel's sums are exact
   double w_total = 0.0;  // sum_{i<j} J_ij
   int device = 0;
 

@@ -67,6 +67,8 @@ hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, 
 hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R, int Kp, int ld, int Rp, int zero,
                              hipStream_t st);
 hipError_t launch_readout(int prec, const void* state, int8_t* spins, size_t count, hipStream_t st);
+// With J8: h_integral tells whether h is integral (then E_int is exact). With J64 instead: h_integral
+// = 1 states that J and h are integral and every sum fits in 2^53, so E_int is exact; else E_int = 0.
 hipError_t launch_energy(const int8_t* J8, const double* J64, const double* h, int h_integral,
                          const int8_t* spins, int N, int R, long long* E_int, double* E, hipStream_t st);
 // Sparse couplings in ELL form (D entries per row, ascending columns, zero-weight padding; values

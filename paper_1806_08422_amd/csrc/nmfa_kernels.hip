@@ -18,7 +18,8 @@
 //                     HBM and writes the next operand copy of S.
 //   readout_kernel    s~ = sign(s) (s = 0 reads +1).
 //   energy_kernel     exact integer energies for integral J (int8) and integral h, or an
-//                     integral pair term plus an FP64 field term summed in ascending i.
+//                     integral pair term plus an FP64 field term summed in ascending i; with
+//                     FP64 couplings the pair sums in FP64 (exact integers for integral J).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -456,7 +457,9 @@ __global__ __launch_bounds__(256) void energy_kernel(const int8_t* __restrict__ 
       if (h) {
         for (int i = 0; i < N; ++i) field += h[i] * (double)s[i];
       }
-      if (E_int) E_int[r] = 0;
+      // integral couplings and fields (the caller checked that every sum stays below 2^53): the
+      // FP64 sums above are exact integers
+      if (E_int) E_int[r] = h_integral ? (long long)totd / 2 + (long long)field : 0;
       E[r] = 0.5 * totd + field;
     }
   }

@@ -42,7 +42,8 @@ J_FORMATS = ("bf16", "fp8_e4m3", "fp4_e2m1", "native", "ell")
 EXPORTS = (
     "nmfa_params_default", "nmfa_create", "nmfa_anneal", "nmfa_anneal_range", "nmfa_spins",
     "nmfa_energies", "nmfa_cuts", "nmfa_energies_of", "nmfa_get_state", "nmfa_set_state",
-    "nmfa_trajectory", "nmfa_info", "nmfa_j_format", "nmfa_last_timing", "nmfa_destroy", "nmfa_noise_words",
+    "nmfa_trajectory", "nmfa_info", "nmfa_j_format", "nmfa_last_timing", "nmfa_debug_raise_abort",
+    "nmfa_destroy", "nmfa_noise_words",
     "nmfa_noise_values", "nmfa_last_error", "nmfa_server_params_default", "nmfa_server_create",
     "nmfa_server_submit", "nmfa_server_poll", "nmfa_server_wait", "nmfa_server_result",
     "nmfa_server_release", "nmfa_server_cancel", "nmfa_server_stats_get", "nmfa_server_destroy",
@@ -68,6 +69,8 @@ class Params(ctypes.Structure):
         ("knot_T", ctypes.POINTER(ctypes.c_double)),
         ("flags", ctypes.c_uint32),
         ("record_iters", ctypes.c_int32),
+        ("n_T_explicit", ctypes.c_int32),
+        ("T_explicit", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -108,6 +111,7 @@ def _load() -> ctypes.CDLL:
         "nmfa_info": ([vp, vp, vp, vp], ctypes.c_int),
         "nmfa_j_format": ([vp, vp], ctypes.c_int),
         "nmfa_last_timing": ([vp, vp, vp, vp], ctypes.c_int),
+        "nmfa_debug_raise_abort": ([vp], ctypes.c_int),
         "nmfa_destroy": ([vp], None),
         "nmfa_noise_words": ([u64, i32, i32, i32, i32, vp], ctypes.c_int),
         "nmfa_noise_values": ([u64, i32, i32, i32, i32, i32, vp], ctypes.c_int),
@@ -160,6 +164,7 @@ class Solver:
     def __init__(self, J: np.ndarray, h: Optional[np.ndarray] = None, precision="bf16",
                  alpha: float = 0.15, sigma: float = 0.15,
                  knots: Optional[Sequence[Tuple[float, float]]] = None, record_iters: int = 0,
+                 temperatures: Optional[Sequence[float]] = None,
                  negate_noise: bool = False, upper_triangular: bool = False,
                  force_step: bool = False, force_xcd: bool = False, force_fenced: bool = False,
                  force_lds_j: bool = False, force_sparse: bool = False, sparse_generic: bool = False):
@@ -198,6 +203,10 @@ class Solver:
             p.n_knots = len(knots)
             p.knot_u = ku.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             p.knot_T = kT.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if temperatures is not None:
+            Tx = np.ascontiguousarray(temperatures, dtype=np.float64)
+            p.n_T_explicit = int(Tx.shape[0])
+            p.T_explicit = Tx.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         handle = ctypes.c_void_p()
         _check(lib.nmfa_create(self.n, _ptr(J), _ptr(hh), ctypes.byref(p), ctypes.byref(handle)))
         self._h = handle
@@ -285,6 +294,10 @@ class Solver:
         f = ctypes.c_int32()
         _check(lib.nmfa_j_format(self._h, ctypes.byref(f)))
         return {"n": n.value, "precision": p.value, "path": PATHS[path.value], "j_format": J_FORMATS[f.value]}
+
+    def debug_raise_abort(self) -> None:
+        """Test hook: set the group kernels' abort word (see nmfa_debug_raise_abort)."""
+        _check(lib.nmfa_debug_raise_abort(self._h))
 
     def last_timing(self) -> dict:
         a, t, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()

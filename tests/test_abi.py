@@ -84,6 +84,21 @@ def test_rejects_bad_parameters_and_schedules():
     assert _create_rc(J, knots=[(0.0, 1.0), (0.5, 0.5), (0.4, 0.2), (1.0, 0.1)])[0] == -1
     assert _create_rc(J, knots=[(0.1, 1.0), (1.0, 0.5)])[0] == -1
     assert _create_rc(J, precision=7)[0] == -1
+    # explicit temperatures (the schedule given point by point) must be finite and positive
+    assert _create_rc(J, temperatures=[1.0, 0.0, 0.5])[0] == -1
+    assert _create_rc(J, temperatures=[1.0, np.nan])[0] == -1
+    assert _create_rc(J, temperatures=[2.0, -1.0])[0] == -1
+
+
+def test_params_struct_matches_the_header():
+    """The binding's nmfa_params has the size the library expects (struct_size check)."""
+    from paper_1806_08422_amd import nmfa
+
+    p = nmfa.Params()
+    nmfa.lib.nmfa_params_default(ctypes.byref(p))
+    assert p.struct_size == ctypes.sizeof(nmfa.Params)
+    assert p.n_T_explicit == 0 and not p.T_explicit
+    assert p.alpha == 0.15 and p.sigma == 0.15
 
 
 def test_server_rejects_bad_parameters():

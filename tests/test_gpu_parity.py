@@ -216,3 +216,22 @@ def test_energies_of_exact(nmfa):
         assert np.array_equal(E, Eo)
         if h is None or np.all(h == np.round(h)):
             assert np.array_equal(Ei, oracle.energies_int(inst.J, inst.h, spins))
+
+
+def test_exact_energies_beyond_int8_couplings(nmfa):
+    """Integral couplings outside the int8 range (|J| up to 300) still give exact integer energies
+    (Eq. 1), through the FP64 energy kernel, for the readout and for given spin vectors."""
+    inst = instances.sk(50, 12)
+    rng = np.random.Generator(np.random.PCG64(3))
+    W = np.triu(rng.integers(-300, 301, (50, 50)).astype(np.float64), 1)
+    J = W + W.T
+    h = np.round(instances.gaussian_fields(50, 40.0, 4))
+    with nmfa.Solver(J, h, precision="fp64") as s:
+        s.anneal(40, 200, 9)
+        spins = s.spins()
+        E, Ei = s.energies()
+        E2, Ei2 = s.energies_of(-spins)
+    assert np.array_equal(Ei, oracle.energies_int(J, h, spins))
+    assert np.array_equal(E, Ei.astype(np.float64))
+    assert np.array_equal(Ei2, oracle.energies_int(J, h, -spins))
+    assert inst.n == 50
