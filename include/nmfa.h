@@ -161,6 +161,23 @@ int nmfa_cuts(nmfa_ctx *c, double *cut);
  * (host, R*n int8 of +1/-1). Synchronous. Errors: EINVAL, ENOMEM, EDEVICE. */
 int nmfa_energies_of(nmfa_ctx *c, int32_t R, const int8_t *spins, double *E, int64_t *E_int);
 
+/* The same energies as nmfa_energies_of, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): it calls no
+ * hipMalloc, hipFree or allocating library routine. Inputs and outputs are DEVICE pointers the
+ * caller owns: d_spins R*n int8 (+1/-1, replica-major; not checked: other values are used as the
+ * integers they are), d_E R doubles, d_E_int R int64 or NULL (0 unless the energies are exact
+ * integers, as for nmfa_energies_of). Asynchronous on hip_stream (NULL = null stream): the
+ * results are ready when the stream reaches them. Where the context keeps the int8 copy of J
+ * (integral |J| <= 127) the kernels take their scratch -- the zero-padded signs,
+ * roundup(R, 64) * roundup(n, 64) bytes rounded up to 256, and R 64-bit partial sums -- from a
+ * fixed device array of NMFA_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; larger
+ * requests fail with NMFA_EINVAL. Every call on one GPU shares that array, so calls that overlap
+ * on one GPU (other streams, other threads) race and must be serialised by the caller.
+ * Errors: EINVAL (NULL pointer, R < 1, scratch too small), EDEVICE. */
+#define NMFA_NOALLOC_SCRATCH_BYTES (16u << 20)
+int nmfa_energies_of_noalloc(nmfa_ctx *c, int32_t R, const int8_t *d_spins, double *d_E, int64_t *d_E_int,
+                             void *hip_stream);
+
 /* Continuous state s after the last call (host, R*n doubles, widened from FP32 on the FP32/BF16
  * paths). Synchronises. Errors: ESTATE, EDEVICE. */
 int nmfa_get_state(nmfa_ctx *c, double *out);

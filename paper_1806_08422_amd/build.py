@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnmfa.so")
-HIP_SOURCES = ["nmfa_kernels.hip", "nmfa_xcd.hip", "nmfa_fill.hip"]
+HIP_SOURCES = ["nmfa_kernels.hip", "nmfa_xcd.hip", "nmfa_fill.hip", "nmfa_noalloc.hip"]
 CXX_SOURCES = ["nmfa_api.cpp", "nmfa_server.cpp"]
 
 ARCH = os.environ.get("NMFA_OFFLOAD_ARCH", "gfx950")

@@ -41,7 +41,7 @@ J_FORMATS = ("bf16", "fp8_e4m3", "fp4_e2m1", "native", "ell")
 # Every function declared in include/nmfa.h (checked by the CPU tests against the header).
 EXPORTS = (
     "nmfa_params_default", "nmfa_create", "nmfa_anneal", "nmfa_anneal_range", "nmfa_spins",
-    "nmfa_energies", "nmfa_cuts", "nmfa_energies_of", "nmfa_get_state", "nmfa_set_state",
+    "nmfa_energies", "nmfa_cuts", "nmfa_energies_of", "nmfa_energies_of_noalloc", "nmfa_get_state", "nmfa_set_state",
     "nmfa_trajectory", "nmfa_info", "nmfa_j_format", "nmfa_last_timing", "nmfa_debug_raise_abort",
     "nmfa_destroy", "nmfa_noise_words",
     "nmfa_noise_values", "nmfa_last_error", "nmfa_server_params_default", "nmfa_server_create",
@@ -105,6 +105,7 @@ def _load() -> ctypes.CDLL:
         "nmfa_energies": ([vp, vp, vp], ctypes.c_int),
         "nmfa_cuts": ([vp, vp], ctypes.c_int),
         "nmfa_energies_of": ([vp, i32, vp, vp, vp], ctypes.c_int),
+        "nmfa_energies_of_noalloc": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
         "nmfa_get_state": ([vp, vp], ctypes.c_int),
         "nmfa_set_state": ([vp, i32, vp], ctypes.c_int),
         "nmfa_trajectory": ([vp, vp], ctypes.c_int),
@@ -271,6 +272,14 @@ class Solver:
         Ei = np.zeros(R, dtype=np.int64)
         _check(lib.nmfa_energies_of(self._h, R, _ptr(s), _ptr(E), _ptr(Ei)))
         return E, Ei
+
+    def energies_of_noalloc(self, R: int, spins_ptr: int, E_ptr: int, E_int_ptr: Optional[int] = None,
+                            stream: Optional[int] = None) -> None:
+        """nmfa_energies_of_noalloc on device buffers (addresses as ints); asynchronous on stream."""
+        st = current_stream_handle() if stream is None else stream
+        _check(lib.nmfa_energies_of_noalloc(self._h, int(R), ctypes.c_void_p(spins_ptr), ctypes.c_void_p(E_ptr),
+                                            ctypes.c_void_p(E_int_ptr) if E_int_ptr else None,
+                                            ctypes.c_void_p(st) if st else None))
 
     def state(self) -> np.ndarray:
         out = np.zeros((self.R, self.n))
