@@ -101,6 +101,19 @@ def measured_valu_instructions(path: str):
     return float(fields["valu_instructions_per_launch"])
 
 
+def energy_deviation(E_a, E_b):
+    """Two-sample comparison of energy distributions: the Kolmogorov-Smirnov statistic (largest
+    gap between the empirical distribution functions) and the difference of the means in units of
+    its standard error."""
+    a, b = np.sort(np.asarray(E_a, dtype=float)), np.sort(np.asarray(E_b, dtype=float))
+    grid = np.concatenate([a, b])
+    ks = float(np.max(np.abs(np.searchsorted(a, grid, side="right") / a.size -
+                             np.searchsorted(b, grid, side="right") / b.size)))
+    se = math.sqrt(a.var(ddof=1) / a.size + b.var(ddof=1) / b.size) if a.size > 1 and b.size > 1 else 0.0
+    d = float(a.mean() - b.mean())
+    return {"ks": ks, "mean_diff": d, "mean_diff_se_units": d / se if se > 0 else 0.0}
+
+
 def timed_anneals(solver, R, t_f, seeds, stream):
     """Run one anneal per seed; return per-anneal wall ms (device-synchronised) and timings."""
     import torch
@@ -131,10 +144,20 @@ def cpu_baseline(inst, t_f_full: int, R_sample: int, target_s: float):
     t0 = time.perf_counter()
     oracle.anneal(inst.J, inst.h, T, R=R_sample, seed=2024, threads=threads)
     dt = time.perf_counter() - t0
+    cpu_model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": inst.n * R_sample * iters / dt,
         "unit": "spin-updates/s",
         "cores": threads,
+        "cpu_model": cpu_model,
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": f"N={inst.n}, replicas 0..{R_sample - 1}, iterations 1..{iters} of the "
                   f"{t_f_full}-iteration schedule, FP64, {dt:.1f} s",
@@ -196,13 +219,16 @@ def serving_leg(nmfa, instances_mod, n_burst: int, n_stream: int, budget_bytes: 
         pending = []
         start = time.perf_counter()
         work = 0
-        for j in stream:
+        for k, j in enumerate(stream):
             delay = start + j.arrival_s - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
             J, h = cache.get(j)
             pending.append(srv.submit(J, h, j.R, j.t_f, j.noise_seed))
             work += J.shape[0] * j.R * j.t_f
+            if (k + 1) % 1000 == 0:
+                print(f"[bench] serving: {k + 1}/{n_stream} requests submitted, "
+                      f"{time.perf_counter() - start:.0f} s", file=sys.stderr, flush=True)
         for t in pending:
             srv.wait(t)
             lat.append(srv.result(t)["latency_ms"])
@@ -231,7 +257,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serving-burst", type=int, default=200)
-    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--serving-budget-gib", type=float, default=2.0)
     ap.add_argument("--serving-child", action="store_true",
                     help="run only the serving leg in this process and print its JSON (the default run "
@@ -350,6 +376,12 @@ def main() -> int:
         "roofline": roofline,
     }
 
+    if args.workload == "g2000":
+        result["config"]["quality_note"] = (
+            "success probability and TTS99 at N=2000 are quoted on the K2000 class (complete graph, "
+            "J=+-1, same kernels) in extra.tts99_n2000_k2000_class: on G(2000,1/2) every sample, FP64 "
+            "included, collapses into the uniform period-2 mode (cut 0), so success there is empty")
+
     if args.calib_copy_mib > 0:
         # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this kernel scale the anneal's
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
@@ -365,10 +397,32 @@ def main() -> int:
         with nmfa.Solver(inst.J, inst.h, precision="fp64") as s64:
             walls, tms = timed_anneals(s64, R, T_F, [77], stream)
         ms64 = walls[0]
+        # Floor for any FP64 implementation of the same iteration: the vendor FP64 matrix product
+        # of one iteration's shape (J [Kp x Kp] times S [Kp x R], Kp = 2048) through torch, times t_f
+        # (no epilogue, no noise, no exchange counted).
+        Ag = torch.randn(2048, 2048, dtype=torch.float64, device="cuda")
+        Bg = torch.randn(2048, R, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            Cg = Ag @ Bg
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(50):
+            Cg = Ag @ Bg
+        ev1.record()
+        torch.cuda.synchronize()
+        gemm_ms = ev0.elapsed_time(ev1) / 50
+        del Ag, Bg, Cg
+        floor_ms = gemm_ms * T_F
         extra["fp64_path"] = {
             "ms_per_anneal": ms64,
             "spin_updates_per_s": spin_updates / (ms64 * 1e-3),
             "speedup_of_headline": (spin_updates / (ms_per_step * 1e-3)) / (spin_updates / (ms64 * 1e-3)),
+            "vendor_fp64_gemm_ms_per_iteration": gemm_ms,
+            "vendor_fp64_gemm_tflops": 2.0 * 2048 * 2048 * R / (gemm_ms * 1e-3) / 1e12,
+            "fp64_floor_ms_per_anneal": floor_ms,
+            "fp64_path_vs_floor": ms64 / floor_ms,
+            "speedup_of_headline_vs_fp64_floor": floor_ms / ms_per_step,
         }
         # Solution quality at N = 2000. On G(2000, 1/2) every sample of the method collapses into the
         # uniform period-2 mode (cut 0, for FP64 as well), so TTS99 is quoted on the K2000 class
@@ -396,6 +450,7 @@ def main() -> int:
             "tts99_s_fp8j_bf16s": tts99(w16[0] * 1e-3 / R, p16),
             "tts99_s_fp64": tts99(w64[0] * 1e-3 / R, p64),
             "mean_E_fp8j_bf16s": float(Ek.mean()), "mean_E_fp64": float(E64.mean()),
+            "energy_deviation_vs_fp64": energy_deviation(Ek, E64),
         }
         extra["g2000_cut_best_headline"] = float((np.triu(inst.J, 1).sum() - E16.min()) / 2)
         # FP8 spin operands (precision fp8j_fp8s) on the headline workload, and their quality on
@@ -414,6 +469,7 @@ def main() -> int:
             "frac_of_bf16_peak": ach8 / PEAK_BF16_TFLOPS,
             "k2000_p_fp8s": p8, "k2000_p_fp64": p64, "k2000_z_vs_fp64": (p8 - p64) / se8 if se8 > 0 else 0.0,
             "k2000_mean_E_fp8s": float(E8k.mean()), "k2000_tts99_s_fp8s": tts99(w8k[0] * 1e-3 / R, p8),
+            "k2000_energy_deviation_vs_fp64": energy_deviation(E8k, E64),
         }
         # N = 100 workloads: dense SK (BF16, R=16384) and dense MAX-CUT (the paper's timing case)
         sk = instances.sk(100, 1)
@@ -432,6 +488,9 @@ def main() -> int:
             "speedup_vs_fp64": msd / msb,
             "E_target": target, "p_bf16": pb, "p_fp64": pd,
             "tts99_s_bf16": tts99(msb * 1e-3 / 16384, pb), "tts99_s_fp64": tts99(msd * 1e-3 / 16384, pd),
+            "z_diff": (pb - pd) / math.sqrt(pb * (1 - pb) / 16384 + pd * (1 - pd) / 16384)
+            if 0 < pb < 1 or 0 < pd < 1 else 0.0,
+            "energy_deviation_vs_fp64": energy_deviation(Eb, Ed),
         }
         # random 3-regular MAX-CUT at N = 2000 (a degree-3 graph, as in the paper's sparse
         # instances): the sparse kernel the library picks against the dense matrix-core kernel
@@ -454,8 +513,9 @@ def main() -> int:
         with nmfa.Solver(ml.J, ml.h, precision="fp32") as s32, nmfa.Solver(ml.J, ml.h, precision="fp64") as s64:
             w32, _ = timed_anneals(s32, 4096, 1000, [51, 52], stream)
             w64, _ = timed_anneals(s64, 4096, 1000, [53], stream)
-            p32 = float(np.mean(s32.energies()[0] <= e0_ml))
-            p64 = float(np.mean(s64.energies()[0] <= e0_ml))
+            E32m, E64m = s32.energies()[0], s64.energies()[0]
+            p32 = float(np.mean(E32m <= e0_ml))
+            p64 = float(np.mean(E64m <= e0_ml))
         ms32 = float(min(w32))
         se = math.sqrt(p32 * (1 - p32) / 4096 + p64 * (1 - p64) / 4096)
         extra["moebius100_fp32"] = {
@@ -463,6 +523,7 @@ def main() -> int:
             "fp64_ms_per_anneal": w64[0], "E_ground": e0_ml, "p_fp32": p32, "p_fp64": p64,
             "z_diff": (p32 - p64) / se if se > 0 else 0.0,
             "tts99_s_fp32": tts99(ms32 * 1e-3 / 4096, p32), "tts99_s_fp64": tts99(w64[0] * 1e-3 / 4096, p64),
+            "energy_deviation_vs_fp64": energy_deviation(E32m, E64m),
         }
         # SK N = 20 on the FP64 path (R = 256, t_f = 1000): success at the enumerated ground energy
         sk20 = instances.sk(20, 1)
@@ -524,13 +585,15 @@ def main() -> int:
         cmd = [sys.executable, os.path.abspath(__file__), "--serving-child",
                "--serving-burst", str(args.serving_burst), "--serving-requests", str(args.serving_requests),
                "--serving-budget-gib", str(args.serving_budget_gib)]
-        proc = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+        print("[bench] serving leg: burst of %d, then a Poisson stream of %d requests" %
+              (args.serving_burst, args.serving_requests), file=sys.stderr, flush=True)
+        proc = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=None, text=True, timeout=900)
         lines = proc.stdout.strip().splitlines()
         if proc.returncode == 0 and lines:
             serving = json.loads(lines[-1])
             serving["process"] = "child process without torch"
         else:
-            serving = {"error": "serving child exited with %d" % proc.returncode, "stderr": proc.stderr[-2000:]}
+            serving = {"error": "serving child exited with %d" % proc.returncode}
         result.setdefault("extra", {})["serving"] = serving
 
     if not args.no_cpu:

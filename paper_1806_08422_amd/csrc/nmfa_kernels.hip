@@ -855,7 +855,7 @@ size_t small_lds_bytes(int prec, int Mp, int stride) {
 // as a tiled matrix product with the fused epilogue. Workgroup (bx, by) owns rows
 // [128 bx, +128) x replicas [128 by, +128); wave w owns rows 64 (w / 2) .. +63 and replicas
 // 64 (w % 2) .. +63 (4 x 4 MFMA tiles of 16 x 16). J [Mp][Kp] and S_cur [Rp][Kp] (both k
-// contiguous) stream through a 3-stage LDS ring of 64-k blocks filled by direct-to-LDS loads
+// contiguous) stream through a 4-stage LDS ring of 64-k blocks filled by direct-to-LDS loads
 // (32 KB per stage: 128 rows of J and 128 replicas of S, 128 bytes each); unit u (8 k) of tile row
 // q sits at u ^ ((q >> 1) & 7) of its row, so the 16 lanes a ds_read_b128 serves hit distinct
 // bank groups. Needs Mp % 128 == 0, S buffers of roundup(R, 128) rows (padding rows zero).

@@ -500,14 +500,20 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
 }
 
 // ---- register-resident J ------------------------------------------------------------------
-// For couplings that FP4 E2M1 holds exactly and N <= 2048: 4 waves per CU, each holding its 32
-// rows of J (FP4, one 32-bit register per 8 couplings: 128 registers at Kp = 2048) for the whole
-// anneal. A workgroup covers 128 rows x 64 replicas, so each widened J fragment feeds four MFMAs
-// and the spin stream per CU is half that of the LDS-resident variant; the whole LDS is a ring of
-// 16 KB spin chunks, of which XRJ_LA are loaded ahead of the one being read. The k loop is unrolled over
-// all chunks, which makes every register index, buffer index, wait count and load offset a
-// compile-time constant.
-constexpr int XRJ_ROWS = 128;                  // rows of J per workgroup (32 per wave)
+// For couplings that FP4 E2M1 holds exactly and N <= 2048. A workgroup covers 128 rows x 64
+// replicas (groups of 64 replicas over P = Mp / 128 workgroups), keeps its rows of J in registers
+// as FP4 (one 32-bit register per 8 couplings) for the whole anneal, and uses the whole LDS as a
+// ring of 16 KB spin chunks (64 replicas x 128 k), of which XRJ_LA are loaded ahead of the one
+// being read. Eight waves, two per SIMD, so that the vector work of one (widening J, noise,
+// epilogue) issues while the other's MFMAs run: the waves form 4 row groups of 32 rows times 2
+// halves of k. Wave (rg, kh) keeps rows 32 rg .. 32 rg + 31 of J for the two 32-k steps 2 kh and
+// 2 kh + 1 of every chunk (64 registers at Kp = 2048) and reads only those steps' spin fragments.
+// The two partial sums of each output meet in LDS (in the ring, idle after the k loop): wave
+// (rg, kh) owns row tile kh of its row group for the epilogue and adds the partner's partial sum of
+// that tile in the fixed order (k half 0) + (k half 1), the same on every workgroup, so results do
+// not depend on placement. The k loop is unrolled over all chunks, which makes every register
+// index, buffer index, wait count and load offset a compile-time constant.
+constexpr int XRJ_ROWS = 128;                  // rows of J per workgroup (32 per row group)
 constexpr int XRJ_RG = 64;                     // replicas per group
 constexpr int XRJ_KC = 128;                    // k per spin chunk (four 32-k MFMA steps)
 constexpr int XRJ_NB = 8;                      // spin chunk buffers in LDS
@@ -519,18 +525,21 @@ __device__ __forceinline__ void static_for(F&& f, std::integer_sequence<int, I..
   (f(std::integral_constant<int, I>{}), ...);
 }
 
-// NCH: number of 128-k chunks (Kp = 128 * NCH). RT: 16-row tiles per wave; the 128 rows are
-// split over 8 / RT waves (RT = 2: 4 waves, one per SIMD; RT = 1: 8 waves, two per SIMD).
-template <int NCH, int RT>
-__global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
-    AnnealArgs a, XcdArgs x) {
-  extern __shared__ __align__(16) unsigned char smem[];  // XRJ_NB chunk buffers
+// NCH: number of 128-k chunks (Kp = 128 NCH).
+template <int NCH>
+__global__ __launch_bounds__(512, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
+  constexpr int KS = 2, RTW = 2, NRG = 4;  // k halves; 16-row tiles per wave; row groups
+  constexpr int NC = NCH, KPW = 2;         // chunks; 32-k steps per wave and chunk
+  constexpr int CHB = XRJ_CHB, NB = XRJ_NB, LA = XRJ_LA;
+  static_assert(8 * (KS - 1) * 4 * 64 * 16 <= XRJ_NB * XRJ_CHB, "the partial sums fit in the ring");
+  extern __shared__ __align__(16) unsigned char smem[];  // the chunk ring
   __shared__ unsigned abort_word;                        // the group barrier's decision
-  constexpr int NB = XRJ_NB;
-  constexpr int DPW = 2 * RT;  // 1 KB direct-to-LDS loads per wave and chunk (16 KB over 8 / RT waves)
-  static_assert(DPW * (XRJ_LA - 1) <= 63, "wait counts fit the vmcnt field");
+  constexpr int DPW = CHB / 1024 / 8;  // 1 KB direct-to-LDS loads per wave and chunk (2)
+  static_assert(DPW * (LA - 1) <= 63, "wait counts fit the vmcnt field");
   const int N = a.N, ks = x.ks;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar registers
+  const int rg = wave % NRG, kh = wave / NRG;  // row group, k half
   const int g4 = lane >> 4, c = lane & 15;
 
   const XcdSlot slot = xcd_register(x, tid);
@@ -540,24 +549,22 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
   const bool xcd_mode = slot.xcd_mode;
   bool aborted = slot.aborted;
 
-  // J of this wave: jr[ch][q][rt] = the 8 FP4 couplings of row rb*128 + 16*RT*wave + 16*rt + c at
-  // k = 128*ch + 8*(4*g4 + q) .. +7 (lane group g4 takes four adjacent 8-k units per chunk; the
-  // spin fragments below use the same k assignment, and a dot product does not depend on the
-  // order of its terms).
-  uint32_t jr[NCH][4][RT];
+  // J of this wave: jr[ch][u][rt] = the 8 FP4 couplings of row rb*128 + 32 rg + 16 rt + c at
+  // k = 128 ch + 8 (4 g4 + 2 kh + u) .. +7: in step 2 kh + u of chunk ch, lane group g4 supplies
+  // the 16-byte unit 4 g4 + 2 kh + u of every spin row (a dot product does not depend on the order
+  // of its terms).
+  uint32_t jr[NC][KPW][RTW];
   {
     const int jrow = 64 * NCH;  // bytes of one FP4 row (Kp / 2)
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
+    for (int rt = 0; rt < RTW; ++rt) {
       const unsigned char* p = reinterpret_cast<const unsigned char*>(a.J) +
-                               (size_t)(rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + c) * jrow + 16 * g4;
+                               (size_t)(rb * XRJ_ROWS + 16 * (RTW * rg + rt) + c) * jrow + 16 * g4 + 8 * kh;
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) {
-        const uint4 v = *reinterpret_cast<const uint4*>(p + 64 * ch);
+      for (int ch = 0; ch < NC; ++ch) {
+        const uint2 v = *reinterpret_cast<const uint2*>(p + 64 * ch);
         jr[ch][0][rt] = v.x;
         jr[ch][1][rt] = v.y;
-        jr[ch][2][rt] = v.z;
-        jr[ch][3][rt] = v.w;
       }
     }
   }
@@ -567,84 +574,62 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
   float* state = reinterpret_cast<float*>(a.state);
   float* traj = reinterpret_cast<float*>(a.traj);
   const float* coef = reinterpret_cast<const float*>(a.coef);
-  float inv[RT][4], hv[RT][4], s[RT][4][4];
-  int row0[RT];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    row0[rt] = rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + 4 * g4;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      inv[rt][v] = inv_g[row0[rt] + v];
-      hv[rt][v] = h_g[row0[rt] + v];
-    }
-  }
+  // outputs of this wave: rows row0 .. row0 + 3 (row tile kh of its row group), replicas
+  // rgroup0 + 16 ct + c
+  const int row0 = rb * XRJ_ROWS + 16 * (RTW * rg + kh) + 4 * g4;
+  float s[4][4];
   const int rgroup0 = group * XRJ_RG;
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) {
     const int r = rgroup0 + 16 * ct + c;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = row0[rt] + v;
-        s[rt][ct][v] = (a.load_state && r < a.R && i < N) ? state[(size_t)r * N + i] : 0.0f;
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int i = row0 + v;
+      s[ct][v] = (a.load_state && r < a.R && i < N) ? state[(size_t)r * N + i] : 0.0f;
+    }
   }
   const float sg = (float)a.sigma;
   const float neg2ln2_s2 = -2.0f * 0.6931471805599453f * sg * sg;
   const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha);
-  // sigma * z for this lane's 4 x (4 RT) spins of iteration tt (noise does not depend on the state,
-  // so it is drawn ahead: while the group barrier of the previous iteration completes)
-  float zn[RT][4][4];
-  // column tiles ct0 .. ct0 + 1 of the draw
+  // sigma * z for this lane's 4 x 4 outputs of iteration tt (drawn ahead, while the group barrier
+  // of the previous iteration completes)
+  float zn[4][4];
   auto draw_noise_half = [&](int tt, int ct0) {
 #pragma unroll
     for (int ct = ct0; ct < ct0 + 2; ++ct)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-        sigma_gauss4_f32(philox4x32_10((uint32_t)(row0[rt] >> 2), (uint32_t)(rgroup0 + 16 * ct + c), (uint32_t)tt, 0u,
-                                       a.key0, a.key1),
-                         neg2ln2_s2, zn[rt][ct]);
+      sigma_gauss4_f32(philox4x32_10((uint32_t)(row0 >> 2), (uint32_t)(rgroup0 + 16 * ct + c), (uint32_t)tt, 0u,
+                                     a.key0, a.key1),
+                       neg2ln2_s2, zn[ct]);
   };
-  // keeps the values of column tiles ct0, ct0 + 1 where they are: the empty volatile statements
-  // read them, so the draw cannot be moved past the code that follows
   auto pin_noise_half = [&](int ct0) {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int ct = ct0; ct < ct0 + 2; ++ct)
 #pragma unroll
-      for (int ct = ct0; ct < ct0 + 2; ++ct)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(zn[rt][ct][v]));
+      for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(zn[ct][v]));
   };
   draw_noise_half(a.t_begin, 0);
   draw_noise_half(a.t_begin, 2);
 
-  // Spin fragments: replica q = 16*ct + c of the chunk, 16-byte unit u = 4*g4 + kq of its 256-byte
-  // row, stored at unit u ^ (q & 15). A ds_read_b128 serves 16 lanes per cycle; their 16 replicas
-  // then hit 16 distinct units, i.e. all 64 banks once, so the reads are conflict free. q & 15
-  // does not depend on ct, so the column tiles are 4 KB apart and one base offset per k step
-  // serves all four.
-  int boff[4];
+  // Spin chunks: replica rows of 16 units of 16 bytes; unit u of replica q sits at u ^ (q & 15),
+  // so the 16 lanes that one ds_read_b128 serves at a time (replicas c = 0..15, one unit) hit all
+  // 64 banks once.
+  int boff[KPW];
 #pragma unroll
-  for (int kq = 0; kq < 4; ++kq) boff[kq] = c * 256 + ((4 * g4 + kq) ^ c) * 16;
-  // Direct-to-LDS loads: a chunk is 16 blocks of 1 KB (4 replicas x 256 bytes); wave w loads
-  // blocks DPW*w .. DPW*w + DPW - 1. Lane l fills unit l % 16 of replica 4*blk + l / 16 from the
-  // global unit that the swizzle puts there.
+  for (int u = 0; u < KPW; ++u) boff[u] = c * 256 + ((4 * g4 + 2 * kh + u) ^ c) * 16;
+  // Direct-to-LDS loads: a chunk is 16 loads of 1 KB (4 replicas each); wave w issues loads
+  // 2 w and 2 w + 1. Lane l fills position l % 16 of replica 4 blk + l / 16 with the global unit
+  // the swizzle puts there.
   unsigned dma_off[DPW];
 #pragma unroll
   for (int u = 0; u < DPW; ++u) {
     const int blk = DPW * wave + u;
-    const int q = 4 * blk + (lane >> 4);
-    const int pu = lane & 15;
-    dma_off[u] = (unsigned)(q * ks + (pu ^ (q & 15)) * 8) * 2u;  // bytes within the group's block
+    const int q = 4 * blk + lane / 16;
+    const int pu = lane % 16;
+    dma_off[u] = (unsigned)(q * ks + (pu ^ (q & 15)) * 8) * 2u;
   }
 
   const __bf16* S0 = reinterpret_cast<const __bf16*>(x.S[0]);
   const __bf16* S1 = reinterpret_cast<const __bf16*>(x.S[1]);
-  // (the LDS operand of the direct-to-LDS builtin is formed from a pointer variable and plain
-  // integers: with the extern shared array itself, or an element of a local array whose size
-  // depends on a template parameter, in that expression the host compilation pass silently
-  // drops the kernel's launch stub)
   unsigned char* ring = smem;
   unsigned* bar = &x.ctl[CTL_BAR + 16 * (int)my_group];
   int epoch = 0;
@@ -659,101 +644,136 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
 #pragma unroll
       for (int u = 0; u < DPW; ++u)
         __builtin_amdgcn_global_load_lds(reinterpret_cast<const __bf16*>(Sg + dma_off[u] + ch * 2 * XRJ_KC),
-                                         ring + buf * XRJ_CHB + (DPW * wave + u) * 1024, 16, 0, 0);
+                                         ring + buf * CHB + (DPW * wave + u) * 1024, 16, 0, 0);
     };
     bf16x8 fb[2][4];  // [register set][column tile]: the spins of one 32-k step
-    // spin fragments of k step kstep (chunk kstep / 4, quarter kstep % 4) into register set kstep % 2
-    auto load = [&](int kstep) {
+    // spin fragments of this wave's step st (chunk st / 2, unit 2 kh + st % 2) into set st % 2
+    auto load = [&](int st) {
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct)
-        fb[kstep & 1][ct] =
-            *reinterpret_cast<const bf16x8*>(smem + ((kstep >> 2) % NB) * XRJ_CHB + boff[kstep & 3] + 4096 * ct);
+        fb[st & 1][ct] = *reinterpret_cast<const bf16x8*>(smem + ((st / KPW) % NB) * CHB + boff[st % KPW] + 4096 * ct);
     };
-    f32x4 acc[RT][4];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
+    f32x4 acc[RTW][4];
 
-    // prologue: the first XRJ_LA chunks in flight, wait for chunk 0, read its first k step. A
-    // deeper prologue only stalls the waves: the direct-to-LDS loads move about 54 bytes per
-    // cycle per CU, so issuing NB - 1 chunks at once holds the waves for about as long as the
-    // transfers take, while chunk 0 alone would already have landed.
-    constexpr int PRO = XRJ_LA < NCH ? XRJ_LA : NCH;
-    static_assert(XRJ_LA <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
+    constexpr int PRO = LA < NC ? LA : NC;
+    static_assert(LA <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
 #pragma unroll
-    for (int q = 0; q < PRO; ++q) issue(q, q);
+    for (int p = 0; p < PRO; ++p) issue(p, p);
     wait_vm<DPW * (PRO - 1)>();
     bare_barrier();
     load(0);
-    // k step ks: the spins of step ks+1 are read into the other register set while the MFMAs
-    // of step ks run. Before the first read of chunk c+1 (in the last step of chunk c) the
-    // workgroup meets at a barrier: chunk c+1 has landed for every wave, and every wave is done
-    // reading chunk c-1. Chunk c+XRJ_LA then goes to buffer (c+XRJ_LA) % NB, which last held
-    // chunk c+XRJ_LA-NB <= c-1.
+    // step st: the spins of step st+1 are read into the other register set while the MFMAs of
+    // step st run. Before the first read of chunk c+1 (in the last step of chunk c) the workgroup
+    // meets at a barrier: chunk c+1 has landed for every wave, and every wave is done reading
+    // chunk c-1, whose buffer then takes chunk c-1+NB.
     static_for(
-        [&](auto kqc) {
-          constexpr int kstep = decltype(kqc)::value;
-          constexpr int ch = kstep >> 2;
-          if constexpr ((kstep & 3) == 3 && ch + 1 < NCH) {
-            constexpr int last_issued = (ch + XRJ_LA - 1 < NCH - 1) ? ch + XRJ_LA - 1 : NCH - 1;
+        [&](auto kc) {
+          constexpr int st = decltype(kc)::value;
+          constexpr int ch = st / KPW;
+          if constexpr (st % KPW == KPW - 1 && ch + 1 < NC) {
+            constexpr int last_issued = (ch + LA - 1 < NC - 1) ? ch + LA - 1 : NC - 1;
             wait_vm<DPW * (last_issued - (ch + 1))>();
             __builtin_amdgcn_sched_barrier(0);
             bare_barrier();
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (ch + XRJ_LA < NCH) issue(ch + XRJ_LA, (ch + XRJ_LA) % NB);
+            if constexpr (ch + LA < NC) issue(ch + LA, (ch + LA) % NB);
           }
-          // The reads of step kstep (issued a step ago) are complete by now; waiting for them before
-          // issuing those of step kstep+1 keeps the MFMAs below free of any LDS wait.
           wait_lds();
-          if constexpr (kstep + 1 < 4 * NCH) load(kstep + 1);
+          if constexpr (st + 1 < KPW * NC) load(st + 1);
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) {
-            const bf16x8 af = fp4x8_to_bf16x8(jr[ch][kstep & 3][rt]);
+          for (int rt = 0; rt < RTW; ++rt) {
+            const bf16x8 af = fp4x8_to_bf16x8(jr[ch][st % KPW][rt]);
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct)
-              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, fb[kstep & 1][ct], acc[rt][ct], 0, 0, 0);
+              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  af, fb[st & 1][ct], st == 0 ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : acc[rt][ct], 0, 0, 0);
           }
           __builtin_amdgcn_sched_barrier(0);
         },
-        std::make_integer_sequence<int, 4 * NCH>{});
+        std::make_integer_sequence<int, KPW * NC>{});
+
+    // Lane-dependent values after the k loop are derived afresh from an opaque copy of the lane
+    // index: computed once before the iteration loop they would stay live across the k loop,
+    // where J, the accumulators and the spin fragments need nearly every register.
+    int lane_e = lane;
+    asm volatile("" : "+v"(lane_e));
+    const int c_e = lane_e & 15;
+    const int row0e = rb * XRJ_ROWS + 16 * (RTW * rg + kh) + 4 * (lane_e >> 4);
+
+    // ---- the two partial sums of each output --------------------------------------------------
+    // Every wave is past its last read of the ring (the last barrier of the k loop came before the
+    // last chunk's reads, so meet again); then each writes its partial sums of the row tiles the
+    // other waves of its row group own: slot ((rg, kh), j, ct) holds tile j (j-th tile other than kh).
+    bare_barrier();
+    f32x4 own[4];  // selected with compile-time indices (a register array indexed by kh would go to scratch)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) own[ct] = acc[0][ct];
+#pragma unroll
+    for (int qq = 1; qq < RTW; ++qq)
+      if (qq == kh) {
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) own[ct] = acc[qq][ct];
+      }
+    f32x4* slots = reinterpret_cast<f32x4*>(smem);
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt) {
+      if (rt == kh) continue;
+      const int j = rt < kh ? rt : rt - 1;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) slots[(((rg * KS + kh) * (KS - 1) + j) * 4 + ct) * 64 + lane_e] = acc[rt][ct];
+    }
+    __syncthreads();
+    f32x4 tot[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      f32x4 sum = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int w = 0; w < KS; ++w) {
+        f32x4 pv;
+        if (w == kh) {
+          pv = own[ct];
+        } else {
+          const int j = kh < w ? kh : kh - 1;
+          pv = slots[(((rg * KS + w) * (KS - 1) + j) * 4 + ct) * 64 + lane_e];
+        }
+        sum = (w == 0) ? pv : sum + pv;  // k half 0, then k half 1
+      }
+      tot[ct] = sum;
+    }
 
     // ---- fused epilogue --------------------------------------------------------------------
     const float coef_t = coef[t - 1];
     const int k_rec = t - a.t_begin;
+    // the normalisers of this lane's rows, re-read every iteration (cache hits) rather than held
+    // in registers across the k loop
+    const f32x4 inv = *reinterpret_cast<const f32x4*>(inv_g + row0e);
+    const f32x4 hv = *reinterpret_cast<const f32x4*>(h_g + row0e);
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
-      const int r = rgroup0 + 16 * ct + c;
+      const int r = rgroup0 + 16 * ct + c_e;
+      __bf16 outv[4];
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        __bf16 outv[4];
+      for (int v = 0; v < 4; ++v) {
+        const float xf = fmaf(tot[ct][v], inv[v], hv[v]);
+        const float phi = a.negate_noise ? xf - zn[ct][v] : xf + zn[ct][v];
+        const float sh = neg_tanh_from_exp2_arg(phi * coef_t);
+        float sv = fmaf(alpha, sh, oma * s[ct][v]);
+        if (row0e + v >= N) sv = 0.0f;
+        s[ct][v] = sv;
+        outv[v] = (__bf16)sv;
+      }
+      *reinterpret_cast<uint2*>(Snext + (size_t)r * ks + row0e) = *reinterpret_cast<const uint2*>(outv);
+      if (traj && k_rec < a.record && r < a.R) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float xf = fmaf(acc[rt][ct][v], inv[rt][v], hv[rt][v]);
-          const float phi = a.negate_noise ? xf - zn[rt][ct][v] : xf + zn[rt][ct][v];
-          const float sh = neg_tanh_from_exp2_arg(phi * coef_t);
-          float sv = fmaf(alpha, sh, oma * s[rt][ct][v]);
-          if (row0[rt] + v >= N) sv = 0.0f;
-          s[rt][ct][v] = sv;
-          outv[v] = (__bf16)sv;
-        }
-        *reinterpret_cast<uint2*>(Snext + (size_t)r * ks + row0[rt]) = *reinterpret_cast<const uint2*>(outv);
-        if (traj && k_rec < a.record && r < a.R) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (row0[rt] + v < N) traj[((size_t)k_rec * a.R + r) * N + row0[rt] + v] = s[rt][ct][v];
-        }
+        for (int v = 0; v < 4; ++v)
+          if (row0e + v < N) traj[((size_t)k_rec * a.R + r) * N + row0e + v] = s[ct][v];
       }
     }
 
     if (t < a.t_end) {
-      // Arrive, draw the next iteration's noise (it does not depend on the state) and wait. The
-      // draw is pinned between arrival and wait, or the compiler would sink it past the wait onto
-      // the critical path; halfway through, the polling thread reads the group counter once, so
-      // that the round trip of that read overlaps the second half of the draw.
+      // arrive, draw the next iteration's noise, wait (as in anneal_xrj); the wait ends with a
+      // workgroup barrier, after which the ring (and the partial sums in it) may be overwritten
       xcd_group_arrive(bar, xcd_mode, tid);
       draw_noise_half(t + 1, 0);
       pin_noise_half(0);
@@ -768,20 +788,21 @@ __global__ __launch_bounds__(64 * 8 / RT, 1) void anneal_xrj(
   }
 
   // ---- final state and readout ---------------------------------------------------------------
+  int lane_f = lane;
+  asm volatile("" : "+v"(lane_f));
+  const int row0f = rb * XRJ_ROWS + 16 * (RTW * rg + kh) + 4 * (lane_f >> 4);
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) {
-    const int r = rgroup0 + 16 * ct + c;
+    const int r = rgroup0 + 16 * ct + (lane_f & 15);
     if (r >= a.R) continue;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = row0[rt] + v;
-        if (i < N) {
-          state[(size_t)r * N + i] = s[rt][ct][v];
-          if (a.spins) a.spins[(size_t)r * N + i] = (s[rt][ct][v] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
-        }
+    for (int v = 0; v < 4; ++v) {
+      const int i = row0f + v;
+      if (i < N) {
+        state[(size_t)r * N + i] = s[ct][v];
+        if (a.spins) a.spins[(size_t)r * N + i] = (s[ct][v] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
       }
+    }
   }
 }
 
@@ -1065,22 +1086,6 @@ int xrj_group_replicas() { return XRJ_RG; }
 int xrj_kp(int n) { return n <= 512 ? 512 : ((n + 255) / 256) * 256; }
 bool xrj_fits(int n) { return xrj_kp(n) <= 2048; }
 
-// 16-row tiles per wave of the register-J kernel: 2 (4 waves of 32 rows, one per SIMD)
-constexpr int XRJ_RT = 2;
-
-static const void* xrj_fn(int Kp) {
-  switch (Kp) {
-    case 512: return (const void*)anneal_xrj<4, XRJ_RT>;
-    case 768: return (const void*)anneal_xrj<6, XRJ_RT>;
-    case 1024: return (const void*)anneal_xrj<8, XRJ_RT>;
-    case 1280: return (const void*)anneal_xrj<10, XRJ_RT>;
-    case 1536: return (const void*)anneal_xrj<12, XRJ_RT>;
-    case 1792: return (const void*)anneal_xrj<14, XRJ_RT>;
-    case 2048: return (const void*)anneal_xrj<16, XRJ_RT>;
-    default: return nullptr;
-  }
-}
-
 int xcd_ctl_words() { return CTL_WORDS; }
 int xcd_rows() { return XCD_ROWS; }
 int xcd_group_replicas() { return XCD_RG; }
@@ -1146,10 +1151,23 @@ hipError_t launch_anneal_xrj8(const AnnealArgs& a, const XcdArgs& x, int groups,
   return launch_resident(fn, groups * x.P, 256, (size_t)XRJ_NB * XRJ8_CHB, a, x, st);
 }
 
+static const void* xrj_fn(int Kp) {
+  switch (Kp) {
+    case 512: return (const void*)anneal_xrj<4>;
+    case 768: return (const void*)anneal_xrj<6>;
+    case 1024: return (const void*)anneal_xrj<8>;
+    case 1280: return (const void*)anneal_xrj<10>;
+    case 1536: return (const void*)anneal_xrj<12>;
+    case 1792: return (const void*)anneal_xrj<14>;
+    case 2048: return (const void*)anneal_xrj<16>;
+    default: return nullptr;
+  }
+}
+
 hipError_t launch_anneal_xrj(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
   const void* fn = xrj_fn(a.Kp);
   if (!fn) return hipErrorInvalidValue;
-  return launch_resident(fn, groups * x.P, 64 * 8 / XRJ_RT, (size_t)XRJ_NB * XRJ_CHB, a, x, st);
+  return launch_resident(fn, groups * x.P, 512, (size_t)XRJ_NB * XRJ_CHB, a, x, st);
 }
 
 hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {

@@ -154,3 +154,43 @@ def test_group_requests_side_by_side_with_capped_launches(nmfa):
             assert np.array_equal(res["spins"], sp)
         st = srv.stats()
         assert st["completed"] == len(jobs) and st["failed"] == 0
+
+
+def test_alone_equals_in_the_mix_on_jobs_sampled_from_the_serving_stream(nmfa):
+    """100 requests sampled from the benchmark's 10,000-request Poisson stream (every 100th job:
+    N in [50, 2000], half dense SK and half random d-regular graphs, fields on a quarter of them,
+    R in {64 .. 1024}) with t_f capped at 250 to bound the runtime: each result is the one the
+    request gets alone, bit for bit, served under the benchmark's 2 GiB admission budget."""
+    import bench
+
+    stream = instances.serving_stream(10000, 80.0, 6)  # the job mix does not depend on the rate
+    sample = stream[::100]
+    assert len(sample) == 100
+    cache = bench._InstanceCache(instances)
+    jobs = []
+    for j in sample:
+        J, h = cache.get(j)
+        jobs.append((J, h, j.R, min(j.t_f, 250), j.noise_seed))
+    kinds = {j.kind for j in sample}
+    assert kinds == {"sk", "regular"} and any(j.with_fields for j in sample)
+    alone = []
+    for J, h, R, t_f, seed in jobs:
+        with nmfa.Solver(J, h, precision="bf16") as s:
+            s.anneal(R, t_f, seed)
+            alone.append((s.energies()[0], s.spins()))
+    print(f"[server] {len(jobs)} sampled jobs run alone", flush=True)
+    with nmfa.Server(precision="bf16", hbm_budget_bytes=2 << 30, max_active=256, chunk_iters=100) as srv:
+        tickets = []
+        for k, (J, h, R, t_f, seed) in enumerate(jobs):
+            tickets.append(srv.submit(J, h, R, t_f, seed))
+            if k % 10 == 9:
+                time.sleep(0.01)  # later requests arrive while earlier ones run
+        for (E, sp), t in zip(alone, tickets):
+            assert srv.wait(t, 300000)
+            res = srv.result(t, spins=True)
+            assert np.array_equal(res["E"], E)
+            assert np.array_equal(res["spins"], sp)
+            srv.release(t)
+        st = srv.stats()
+        assert st["completed"] == len(jobs) and st["failed"] == 0
+        assert st["peak_bytes"] <= 2 << 30
