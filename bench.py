@@ -37,9 +37,12 @@ PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP8_TFLOPS = 5000.0
 PEAK_HBM_GBS = 8000.0
-# Vector ALU issue peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
-# (half the 157.3 TFLOP/s FP32 vector figure, which counts packed FMAs as 4 flops per lane)
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Vector ALU: 256 CUs x 4 SIMDs; each SIMD issues one wave instruction (64 lanes over 4 cycles of
+# 16 lanes) at a time, at 2.4 GHz: 2.46e12 SIMD-cycles/s, i.e. 39.3 T lane-operations/s at full
+# rate without packed FP32 (half the 157.3 TFLOP/s FP32 vector figure, which counts packed FMAs as
+# 4 flops per lane). A VALU-bound kernel is measured by the share of SIMD cycles its vector
+# instructions keep busy (counters), which also accounts for the half-rate transcendentals.
+PEAK_SIMD_CYCLES = 256 * 4 * 2.4e9
 
 
 def tts99(t_sample_s: float, p: float) -> float:
@@ -68,6 +71,26 @@ def measured_traffic(path: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def measured_busy_xrj(path: str):
+    """MFMA and VALU busy fractions of the headline kernel from the committed counter summary, or
+    None when the kernel source changed since the counters were taken (or another path ran)."""
+    import hashlib
+
+    prof = os.path.join(ROOT, "profiles", "anneal_xrj_g2000_r1024_tf5000_mfma_valu.md")
+    src = os.path.join(ROOT, "paper_1806_08422_amd", "csrc", "nmfa_xcd.hip")
+    keys = ("valu_busy_frac", "mfma_busy_frac", "kernel_source_sha256", "kernel_path")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
+                      if ": " in line and line.split(": ", 1)[0] in keys)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != sha or fields.get("kernel_path", "").strip() != path:
+        return None
+    return {"mfma_busy_frac": float(fields["mfma_busy_frac"]), "valu_busy_frac": float(fields["valu_busy_frac"]),
+            "summary": "profiles/anneal_xrj_g2000_r1024_tf5000_mfma_valu.md"}
+
+
 def ground_energy_enumerated(J: np.ndarray) -> float:
     """Minimum of H(s) = sum_{i<j} J_ij s_i s_j over all s in {-1, +1}^n (h = 0, so s_0 = +1 is
     enough by the symmetry H(s) = H(-s)), by enumeration in blocks; for n <= 24."""
@@ -82,14 +105,16 @@ def ground_energy_enumerated(J: np.ndarray) -> float:
     return best
 
 
-def measured_valu_instructions(path: str):
-    """Wave-level VALU instructions per launch of the sparse kernel on the 3-regular workload, from
-    the committed counter summary, or None when the kernel source changed since (or another path ran)."""
+def measured_valu_busy(path: str, profile: str):
+    """VALU busy fraction of the annealing kernel from a committed counter summary: the share of
+    SIMD cycles (over all 1024 SIMDs, while the kernel runs) in which a vector instruction executes,
+    from SQ_ACTIVE_INST_VALU (quad-cycles, summed over SIMDs) and GRBM_GUI_ACTIVE. None when the
+    kernel source changed since the counters were taken, or another kernel path ran."""
     import hashlib
 
-    prof = os.path.join(ROOT, "profiles", "anneal_sparse_rq_d3_n2000_r1024_tf5000_valu.md")
+    prof = os.path.join(ROOT, "profiles", profile)
     src = os.path.join(ROOT, "paper_1806_08422_amd", "csrc", "nmfa_kernels.hip")
-    keys = ("valu_instructions_per_launch", "kernel_source_sha256", "kernel_path")
+    keys = ("valu_busy_frac", "mfma_busy_frac", "kernel_source_sha256", "kernel_path")
     try:
         fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
                       if ": " in line and line.split(": ", 1)[0] in keys)
@@ -98,7 +123,7 @@ def measured_valu_instructions(path: str):
         return None
     if fields.get("kernel_source_sha256", "").strip() != sha or fields.get("kernel_path", "").strip() != path:
         return None
-    return float(fields["valu_instructions_per_launch"])
+    return float(fields["valu_busy_frac"])
 
 
 def energy_deviation(E_a, E_b):
@@ -245,11 +270,12 @@ def serving_leg(nmfa, instances_mod, n_burst: int, n_stream: int, budget_bytes: 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("g2000", "d3_2000", "g2000_fp8s", "sk8192"), default="g2000",
+    ap.add_argument("--workload", choices=("g2000", "d3_2000", "g2000_fp8s", "sk8192", "sk100"), default="g2000",
                     help="g2000: dense G(2000, 0.5) MAX-CUT (default); d3_2000: random 3-regular "
                          "MAX-CUT at N = 2000 on the sparse kernel; g2000_fp8s: the default workload "
                          "with FP8 spin operands (precision fp8j_fp8s); sk8192: dense SK at N = 8192, "
-                         "R = 1024, t_f = 200 on the tiled per-iteration kernel (BF16)")
+                         "R = 1024, t_f = 200 on the tiled per-iteration kernel (BF16); sk100: dense SK "
+                         "at N = 100, R = 16384, t_f = 1000 on the persistent small kernel (BF16)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -288,11 +314,14 @@ def main() -> int:
 
     N, R, T_F = 2000, 1024, 5000
     big = args.workload == "sk8192"
+    small = args.workload == "sk100"
     if big:
         N, T_F = 8192, 200
+    if small:
+        N, R, T_F = 100, 16384, 1000
     dense = args.workload in ("g2000", "g2000_fp8s", "sk8192")
-    prec_main = {"g2000_fp8s": "fp8j_fp8s", "sk8192": "bf16"}.get(args.workload, "fp8j_bf16s")
-    if big:
+    prec_main = {"g2000_fp8s": "fp8j_fp8s", "sk8192": "bf16", "sk100": "bf16"}.get(args.workload, "fp8j_bf16s")
+    if big or small:
         inst = instances.sk(N, 1)
     else:
         inst = instances.gnp(N, 0.5, 1) if dense else instances.random_regular(N, 3, 1)
@@ -340,18 +369,25 @@ def main() -> int:
             "kernel_avg_ms": kernel_ms, "launches_per_step": tm["launches"],
             "flops_per_launch": flops_per_launch,
         }
+        if not (fp8s or big):
+            roofline["busy_counters"] = measured_busy_xrj(path)
     else:
-        workload = ("random 3-regular MAX-CUT, N=2000, J in {0,1}, h=0, R=1024, t_f=5000, sparse "
-                    "(ELL) kernel, FP32 arithmetic")
-        # VALU-bound: the per-replica epilogue (Philox, Box-Muller, tanh) dominates; achieved =
-        # counted VALU lane-operations (wave instructions x 64) per second of the kernel
-        vi = measured_valu_instructions(path)
-        ach = None if vi is None else vi * 64 / (kernel_ms * 1e-3) / 1e12
+        if small:
+            workload = ("dense SK N=100, J in {-1,+1}, h=0, R=16384, t_f=1000, J and spins BF16 / FP32 "
+                        "accumulate, persistent small kernel")
+            prof = "anneal_small_sk100_r16384_tf1000_valu_busy.md"
+        else:
+            workload = ("random 3-regular MAX-CUT, N=2000, J in {0,1}, h=0, R=1024, t_f=5000, sparse "
+                        "(ELL) kernel, FP32 arithmetic")
+            prof = "anneal_sparse_rq_d3_n2000_r1024_tf5000_valu_busy.md"
+        # VALU-bound: the per-replica epilogue (Philox, Box-Muller, tanh) dominates; the roofline is
+        # the share of SIMD cycles the kernel's vector instructions keep busy, from counters
+        busy = measured_valu_busy(path, prof)
         roofline = {
-            "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-            "frac": None if ach is None else ach / PEAK_VALU_TOPS, "traffic": None,
-            "kernel_avg_ms": kernel_ms, "launches_per_step": tm["launches"],
-            "valu_instructions_per_launch": vi,
+            "bound": "alu", "achieved": None if busy is None else busy * PEAK_SIMD_CYCLES / 1e12,
+            "peak": PEAK_SIMD_CYCLES / 1e12, "unit": "T SIMD-cycles/s with VALU busy",
+            "frac": busy, "traffic": None, "kernel_avg_ms": kernel_ms, "launches_per_step": tm["launches"],
+            "counter_summary": "profiles/" + prof,
         }
 
     result = {
@@ -365,11 +401,11 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("fp8" if prec_main == "fp8j_fp8s" else "bf16") if dense else "f32",
+        "dtype": ("fp8" if prec_main == "fp8j_fp8s" else "bf16") if (dense or small) else "f32",
         "data": "synthetic",
         "config": {
             "workload": workload,
-            "n": N, "replicas": R, "t_f": T_F, "precision": prec_main if dense else "fp8j_bf16s", "kernel_path": path,
+            "n": N, "replicas": R, "t_f": T_F, "precision": prec_main, "kernel_path": path,
             "j_storage": jfmt,
             "parallelism": "single GPU",
         },
