@@ -470,7 +470,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->sp_RB = sp_rb;
   } else if (c->path == 2 && x_rj) {
     c->xvar = fp8s ? 2 : 1;
-    c->Mp = (int)round_up(n, xrj_rows());
+    c->Mp = (int)round_up(n, xrj_rows(fp8s ? 1 : 0));
     c->Kp = xrj_kp(n);
     c->lds_stride = 0;
     c->jfmt = x_jfmt;
@@ -777,9 +777,9 @@ extern "C" int nmfa_anneal_range(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_
 
 bool ctx_group_shape(const nmfa_ctx* c, int32_t R, int* P, int* G) {
   if (c->path != 2) return false;
-  const int Rg = c->xvar ? xrj_group_replicas() : xcd_group_replicas();
+  const int Rg = c->xvar ? xrj_group_replicas(c->xvar == 2) : xcd_group_replicas();
   *G = (R + Rg - 1) / Rg;
-  *P = c->Mp / (c->xvar ? xrj_rows() : xcd_rows());
+  *P = c->Mp / (c->xvar ? xrj_rows(c->xvar == 2) : xcd_rows());
   return true;
 }
 
@@ -800,9 +800,9 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     c->launches = 1;
     HIP_TRY(hipEventRecord(c->evm, st));
   } else if (c->path == 2) {
-    const int Rg = c->xvar ? xrj_group_replicas() : xcd_group_replicas();
+    const int Rg = c->xvar ? xrj_group_replicas(c->xvar == 2) : xcd_group_replicas();
     const int G = (R + Rg - 1) / Rg;
-    const int P = c->Mp / (c->xvar ? xrj_rows() : xcd_rows());
+    const int P = c->Mp / (c->xvar ? xrj_rows(c->xvar == 2) : xcd_rows());
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
     int width = std::min(cus, 256);  // the control block serves 256 workgroups

@@ -43,12 +43,13 @@ hipError_t launch_anneal_small_batched(int prec, const AnnealArgs* jobs, const i
                                        int max_Mp, size_t lds, hipStream_t st);
 // jfmt: format of J in global memory and LDS: 0 = BF16, 1 = FP8 E4M3, 2 = FP4 E2M1
 hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
-// Register-resident-J variant (FP4 J): 128 rows per workgroup, groups of 64 replicas, Kp = xrj_kp(n).
+// Register-resident-J variant (FP4 J), Kp = xrj_kp(n): BF16 spins with 256 rows per workgroup and
+// groups of 32 replicas; FP8 spins (launch_anneal_xrj8) with 128 rows and groups of 64 replicas.
 hipError_t launch_anneal_xrj(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
 // The same decomposition with FP8 E4M3 spin operands (FP4 x FP8 scaled MFMA); S holds bytes.
 hipError_t launch_anneal_xrj8(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st);
-int xrj_rows();
-int xrj_group_replicas();
+int xrj_rows(int fp8_spins);
+int xrj_group_replicas(int fp8_spins);
 int xrj_kp(int n);
 bool xrj_fits(int n);
 size_t xcd_j_lds_bytes(int jfmt, int Kp);

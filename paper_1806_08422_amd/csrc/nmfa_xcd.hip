@@ -499,48 +499,62 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
   }
 }
 
-// ---- register-resident J ------------------------------------------------------------------
-// For couplings that FP4 E2M1 holds exactly and N <= 2048. A workgroup covers 128 rows x 64
-// replicas (groups of 64 replicas over P = Mp / 128 workgroups), keeps its rows of J in registers
-// as FP4 (one 32-bit register per 8 couplings) for the whole anneal, and uses the whole LDS as a
-// ring of 16 KB spin chunks (64 replicas x 128 k), of which XRJ_LA are loaded ahead of the one
-// being read. Eight waves, two per SIMD, so that the vector work of one (widening J, noise,
-// epilogue) issues while the other's MFMAs run: the waves form 4 row groups of 32 rows times 2
-// halves of k. Wave (rg, kh) keeps rows 32 rg .. 32 rg + 31 of J for the two 32-k steps 2 kh and
-// 2 kh + 1 of every chunk (64 registers at Kp = 2048) and reads only those steps' spin fragments.
-// The two partial sums of each output meet in LDS (in the ring, idle after the k loop): wave
-// (rg, kh) owns row tile kh of its row group for the epilogue and adds the partner's partial sum of
-// that tile in the fixed order (k half 0) + (k half 1), the same on every workgroup, so results do
-// not depend on placement. The k loop is unrolled over all chunks, which makes every register
-// index, buffer index, wait count and load offset a compile-time constant.
-constexpr int XRJ_ROWS = 128;                  // rows of J per workgroup (32 per row group)
-constexpr int XRJ_RG = 64;                     // replicas per group
-constexpr int XRJ_KC = 128;                    // k per spin chunk (four 32-k MFMA steps)
-constexpr int XRJ_NB = 8;                      // spin chunk buffers in LDS
-constexpr int XRJ_LA = 4;                      // chunks in flight ahead of the one being read
-constexpr int XRJ_CHB = XRJ_RG * XRJ_KC * 2;   // bytes of one chunk: 64 replicas x 128 k, BF16
+// ---- register-resident J, BF16 spins -------------------------------------------------------
+// For couplings that FP4 E2M1 holds exactly and N <= 2048. A workgroup covers 256 rows x 32
+// replicas (groups of 32 replicas over P = Mp / 256 workgroups) with four waves, one per SIMD:
+//   * Wave w keeps rows 64 w .. 64 w + 63 of the workgroup's block of J for every k in registers,
+//     as FP4 (one 32-bit register per 8 couplings: 256 registers at Kp = 2048), so each output's
+//     whole sum stays in one wave. Per 16-k step it widens two J fragments (two 32-row tiles) and
+//     runs two v_mfma_f32_32x32x16_bf16 on the step's spin fragment, read from LDS two steps ahead.
+//   * The group's BF16 spins stream through LDS in 8 KB chunks (32 replicas x 128 k), a ring of
+//     XRB_NB buffers filled XRB_LA chunks ahead by direct-to-LDS buffer loads: a CU receives 128 KB
+//     of spins per iteration.
+//   * The chunks are visited starting at the workgroup's own rows (two chunks) and wrapping around,
+//     the same order on every pass. The spins of the own rows are written into the ring by the
+//     epilogue, so an iteration starts on them while the loads of the other chunks are in flight.
+//   * The Philox noise of the next iteration and its field term (h_i + z) / (T_t norm_i) are
+//     computed while the group barrier completes (half before this workgroup's arrival, while its
+//     spin stores complete, half after it).
+//   * The epilogue (exp2, reciprocal, damped update) runs on the accumulator layout; the FP32 master
+//     state stays in registers.
+// The k loop is unrolled over all chunks, so every register index, buffer index, wait count and
+// load offset is a compile-time constant.
+constexpr int XRB_ROWS = 256;                  // rows of J per workgroup (64 per wave)
+constexpr int XRB_RG = 32;                     // replicas per group
+constexpr int XRB_KC = 128;                    // k per spin chunk
+constexpr int XRB_NB = 16;                     // spin chunk buffers in LDS
+constexpr int XRB_LA = 4;                      // chunks in flight ahead of the one being read
+constexpr int XRB_CHB = XRB_RG * XRB_KC * 2;   // bytes of one chunk: 32 replicas x 128 k, BF16
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 template <class F, int... I>
 __device__ __forceinline__ void static_for(F&& f, std::integer_sequence<int, I...>) {
   (f(std::integral_constant<int, I>{}), ...);
 }
 
+// Output layout of v_mfma_f32_32x32x16_bf16: lane l holds column l % 32 and, in accumulator
+// element i, row 8 (i / 4) + 4 (l / 32) + i % 4: four quads of consecutive rows, each the four
+// Gaussians of one Philox call.
+//
 // NCH: number of 128-k chunks (Kp = 128 NCH).
 template <int NCH>
-__global__ __launch_bounds__(512, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
-  constexpr int KS = 2, RTW = 2, NRG = 4;  // k halves; 16-row tiles per wave; row groups
-  constexpr int NC = NCH, KPW = 2;         // chunks; 32-k steps per wave and chunk
-  constexpr int CHB = XRJ_CHB, NB = XRJ_NB, LA = XRJ_LA;
-  static_assert(8 * (KS - 1) * 4 * 64 * 16 <= XRJ_NB * XRJ_CHB, "the partial sums fit in the ring");
+__global__ __launch_bounds__(256, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
+  constexpr int NC = NCH, NST = 8, NSTEP = NC * NST;  // chunks; 16-k steps per chunk
+  constexpr int D = 2;                                // spin fragments read D steps ahead
+  constexpr int OWN = XRB_ROWS / XRB_KC;              // chunks of the workgroup's own rows (2)
+  constexpr int CHB = XRB_CHB, NB = XRB_NB, LA = XRB_LA;
+  constexpr int DPW = CHB / 1024 / 4;                 // 1 KB direct-to-LDS loads per wave and chunk (2)
+  static_assert(NC >= OWN + 1 && NC <= NB, "own chunks keep buffers 0 and 1 to themselves");
+  static_assert(DPW * LA <= 63, "wait counts fit the vmcnt field");
+  static_assert(LA <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
   extern __shared__ __align__(16) unsigned char smem[];  // the chunk ring
   __shared__ unsigned abort_word;                        // the group barrier's decision
-  constexpr int DPW = CHB / 1024 / 8;  // 1 KB direct-to-LDS loads per wave and chunk (2)
-  static_assert(DPW * (LA - 1) <= 63, "wait counts fit the vmcnt field");
+  __shared__ f32x4 rowc[2][XRB_ROWS / 4];                // 1 / norm_i and h_i / norm_i of the workgroup's rows
   const int N = a.N, ks = x.ks;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar registers
-  const int rg = wave % NRG, kh = wave / NRG;  // row group, k half
-  const int g4 = lane >> 4, c = lane & 15;
+  const int g = lane >> 5, c = lane & 31;
 
   const XcdSlot slot = xcd_register(x, tid);
   const unsigned my_group = slot.my_group;
@@ -549,76 +563,61 @@ __global__ __launch_bounds__(512, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
   const bool xcd_mode = slot.xcd_mode;
   bool aborted = slot.aborted;
 
-  // J of this wave: jr[ch][u][rt] = the 8 FP4 couplings of row rb*128 + 32 rg + 16 rt + c at
-  // k = 128 ch + 8 (4 g4 + 2 kh + u) .. +7: in step 2 kh + u of chunk ch, lane group g4 supplies
-  // the 16-byte unit 4 g4 + 2 kh + u of every spin row (a dot product does not depend on the order
-  // of its terms).
-  uint32_t jr[NC][KPW][RTW];
+  // J of this wave: jr[i][st][at] = the 8 FP4 couplings of row rb*256 + 64 wave + 32 at + c at
+  // k = 128 ch + 16 st + 8 g .. +7 with ch = (2 rb + i) mod NC. Lane group g supplies k octet g of
+  // every 16-k step, for J and spins alike (a dot product does not depend on the order of its terms).
+  uint32_t jr[NC][NST][2];
   {
-    const int jrow = 64 * NCH;  // bytes of one FP4 row (Kp / 2)
+    const int jrow = 64 * NC;  // bytes of one FP4 row (Kp / 2)
 #pragma unroll
-    for (int rt = 0; rt < RTW; ++rt) {
+    for (int at = 0; at < 2; ++at) {
       const unsigned char* p = reinterpret_cast<const unsigned char*>(a.J) +
-                               (size_t)(rb * XRJ_ROWS + 16 * (RTW * rg + rt) + c) * jrow + 16 * g4 + 8 * kh;
+                               (size_t)(rb * XRB_ROWS + 64 * wave + 32 * at + c) * jrow + 4 * g;
 #pragma unroll
-      for (int ch = 0; ch < NC; ++ch) {
-        const uint2 v = *reinterpret_cast<const uint2*>(p + 64 * ch);
-        jr[ch][0][rt] = v.x;
-        jr[ch][1][rt] = v.y;
+      for (int i = 0; i < NC; ++i) {
+        const int ch = (OWN * rb + i) % NC;
+#pragma unroll
+        for (int st = 0; st < NST; ++st) jr[i][st][at] = *reinterpret_cast<const uint32_t*>(p + 64 * ch + 8 * st);
       }
     }
   }
 
-  const float* inv_g = reinterpret_cast<const float*>(a.inv_norm);
-  const float* h_g = reinterpret_cast<const float*>(a.hterm);
+  // the per-row constants live in LDS for the whole anneal (the epilogue reads them every iteration)
+  if (tid < XRB_ROWS / 4) {
+    rowc[0][tid] = reinterpret_cast<const f32x4*>(a.inv_norm)[rb * (XRB_ROWS / 4) + tid];
+    rowc[1][tid] = reinterpret_cast<const f32x4*>(a.hterm)[rb * (XRB_ROWS / 4) + tid];
+  }
+  __syncthreads();
   float* state = reinterpret_cast<float*>(a.state);
   float* traj = reinterpret_cast<float*>(a.traj);
   const float* coef = reinterpret_cast<const float*>(a.coef);
-  // outputs of this wave: rows row0 .. row0 + 3 (row tile kh of its row group), replicas
-  // rgroup0 + 16 ct + c
-  const int row0 = rb * XRJ_ROWS + 16 * (RTW * rg + kh) + 4 * g4;
-  float s[4][4];
-  const int rgroup0 = group * XRJ_RG;
+  // outputs of this lane: rows row0 + 32 at + 8 j + v (at = 0, 1; j, v = 0..3), replica rgroup0 + c
+  const int row0 = rb * XRB_ROWS + 64 * wave + 4 * g;
+  const int rgroup0 = group * XRB_RG;
+  float s[2][16];
+  {
+    const int r = rgroup0 + c;
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int r = rgroup0 + 16 * ct + c;
+    for (int at = 0; at < 2; ++at)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = row0 + v;
-      s[ct][v] = (a.load_state && r < a.R && i < N) ? state[(size_t)r * N + i] : 0.0f;
-    }
+      for (int i = 0; i < 16; ++i) {
+        const int row = row0 + 32 * at + 8 * (i / 4) + i % 4;
+        s[at][i] = (a.load_state && r < a.R && row < N) ? state[(size_t)r * N + row] : 0.0f;
+      }
   }
   const float sg = (float)a.sigma;
   const float neg2ln2_s2 = -2.0f * 0.6931471805599453f * sg * sg;
-  const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha);
-  // sigma * z for this lane's 4 x 4 outputs of iteration tt (drawn ahead, while the group barrier
-  // of the previous iteration completes)
-  float zn[4][4];
-  auto draw_noise_half = [&](int tt, int ct0) {
-#pragma unroll
-    for (int ct = ct0; ct < ct0 + 2; ++ct)
-      sigma_gauss4_f32(philox4x32_10((uint32_t)(row0 >> 2), (uint32_t)(rgroup0 + 16 * ct + c), (uint32_t)tt, 0u,
-                                     a.key0, a.key1),
-                       neg2ln2_s2, zn[ct]);
-  };
-  auto pin_noise_half = [&](int ct0) {
-#pragma unroll
-    for (int ct = ct0; ct < ct0 + 2; ++ct)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(zn[ct][v]));
-  };
-  draw_noise_half(a.t_begin, 0);
-  draw_noise_half(a.t_begin, 2);
+  const float alpha2 = (float)(2.0 * a.alpha), nalpha = (float)(-a.alpha), oma = (float)(1.0 - a.alpha);
 
   // Spin chunks: replica rows of 16 units of 16 bytes; unit u of replica q sits at u ^ (q & 15),
-  // so the 16 lanes that one ds_read_b128 serves at a time (replicas c = 0..15, one unit) hit all
-  // 64 banks once.
-  int boff[KPW];
+  // so the 16 lanes that one ds_read_b128 serves at a time (16 replicas, one unit) hit all 64
+  // banks once. Step st reads unit 2 st + g of replica c.
+  int boff[NST];
 #pragma unroll
-  for (int u = 0; u < KPW; ++u) boff[u] = c * 256 + ((4 * g4 + 2 * kh + u) ^ c) * 16;
-  // Direct-to-LDS loads: a chunk is 16 loads of 1 KB (4 replicas each); wave w issues loads
-  // 2 w and 2 w + 1. Lane l fills position l % 16 of replica 4 blk + l / 16 with the global unit
-  // the swizzle puts there.
+  for (int st = 0; st < NST; ++st) boff[st] = c * 256 + (((2 * st + g) ^ (c & 15)) * 16);
+  // Direct-to-LDS loads: a chunk is 8 loads of 1 KB (4 replicas each); wave w issues loads
+  // DPW w .. DPW w + DPW - 1. Lane l fills position l % 16 of replica 4 blk + l / 16 with the global
+  // unit the swizzle puts there.
   unsigned dma_off[DPW];
 #pragma unroll
   for (int u = 0; u < DPW; ++u) {
@@ -627,6 +626,47 @@ __global__ __launch_bounds__(512, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
     const int pu = lane % 16;
     dma_off[u] = (unsigned)(q * ks + (pu ^ (q & 15)) * 8) * 2u;
   }
+  // where this lane's four new spins of row quad (at, j) go in the own chunks (ring buffers 0, 1):
+  // workgroup row 64 wave + 32 at + 8 j + 4 g is k = 64 (wave & 1) + 32 at + 8 j + 4 g of own chunk
+  // wave / 2, i.e. half g of unit 8 (wave & 1) + 4 at + j
+  auto own_off = [&](int at, int j, int ln) {
+    const int q = ln & 31;
+    return (wave >> 1) * CHB + q * 256 + (((8 * (wave & 1) + 4 * at + j) ^ (q & 15)) * 16) + 8 * (ln >> 5);
+  };
+
+  // w = (h_i + sigma z) / (T_t norm_i) for this lane's outputs of iteration tt (exp2 units), with the
+  // Philox noise of (row quad, replica, tt). Drawn one iteration ahead, while the group barrier of
+  // the previous iteration completes.
+  float w[2][16];
+  float coef_next = coef[a.t_begin - 1];
+  // h_i / norm_i of this lane's rows (quad (at, j) is entry 16 wave + 8 at + 2 j + g of the workgroup's
+  // rows), read again in the epilogue for the next draws
+  f32x4 hrow[2][4];
+#pragma unroll
+  for (int at = 0; at < 2; ++at)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hrow[at][j] = rowc[1][16 * wave + 8 * at + 2 * j + g];
+  auto draw = [&](int tt, int d0, int nd, float coef_tt) {
+    const float coef_z = a.negate_noise ? -coef_tt : coef_tt;
+#pragma unroll
+    for (int d = d0; d < d0 + nd; ++d) {
+      const int at = d >> 2, j = d & 3;
+      float z[4];
+      sigma_gauss4_f32(philox4x32_10((uint32_t)((row0 + 32 * at + 8 * j) >> 2), (uint32_t)(rgroup0 + c),
+                                     (uint32_t)tt, 0u, a.key0, a.key1),
+                       neg2ln2_s2, z);
+      const f32x4 hc = hrow[at][j] * coef_tt;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) w[at][4 * j + v] = fmaf(z[v], coef_z, hc[v]);
+    }
+  };
+  auto pin_noise = [&](int d0, int nd) {
+#pragma unroll
+    for (int d = d0; d < d0 + nd; ++d)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(w[d >> 2][4 * (d & 3) + v]));
+  };
+  draw(a.t_begin, 0, 8, coef_next);
 
   const __bf16* S0 = reinterpret_cast<const __bf16*>(x.S[0]);
   const __bf16* S1 = reinterpret_cast<const __bf16*>(x.S[1]);
@@ -636,153 +676,148 @@ __global__ __launch_bounds__(512, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
   __syncthreads();
 
   for (int t = a.t_begin; t <= a.t_end && !aborted; ++t) {
+    const float coef_t = coef_next;
     const unsigned char* Sg =
-        reinterpret_cast<const unsigned char*>(((t & 1) ? S1 : S0) + (size_t)group * XRJ_RG * ks);
+        reinterpret_cast<const unsigned char*>(((t & 1) ? S1 : S0) + (size_t)group * XRB_RG * ks);
     __bf16* Snext = const_cast<__bf16*>((t & 1) ? S0 : S1);
+    const bool own_in_lds = t > a.t_begin;
 
-    auto issue = [&](int ch, int buf) {
+    // the chunk offsets are recomputed every iteration from an opaque copy of rb: held across the
+    // loop they would occupy scalar registers for every chunk
+    int rb_t = rb;
+    asm volatile("" : "+s"(rb_t));
+    // The direct-to-LDS loads go through a buffer resource over the group's spin rows (reads past
+    // it return 0) rather than the global form, which the compiler treats as a flat access to both
+    // memory and LDS and then follows with full LDS waits before every use of an LDS read.
+    const __amdgpu_buffer_rsrc_t srs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(Sg), 0, XRB_RG * ks * 2, 0x00020000);
+    auto issue = [&](int i, int buf) {
+      int ch = OWN * rb_t + i;
+      if (ch >= NC) ch -= NC;
 #pragma unroll
       for (int u = 0; u < DPW; ++u)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const __bf16*>(Sg + dma_off[u] + ch * 2 * XRJ_KC),
-                                         ring + buf * CHB + (DPW * wave + u) * 1024, 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(srs, ring + buf * CHB + (DPW * wave + u) * 1024, 16, dma_off[u],
+                                                 ch * 2 * XRB_KC, 0, 0);
     };
-    bf16x8 fb[2][4];  // [register set][column tile]: the spins of one 32-k step
-    // spin fragments of this wave's step st (chunk st / 2, unit 2 kh + st % 2) into set st % 2
-    auto load = [&](int st) {
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        fb[st & 1][ct] = *reinterpret_cast<const bf16x8*>(smem + ((st / KPW) % NB) * CHB + boff[st % KPW] + 4096 * ct);
+    bf16x8 fb[D + 1];  // [register set]: the spins of one 16-k step
+    auto load = [&](int sidx) {
+      fb[sidx % (D + 1)] = *reinterpret_cast<const bf16x8*>(smem + ((sidx / NST) % NB) * CHB + boff[sidx % NST]);
     };
-    f32x4 acc[RTW][4];
+    f32x16 acc[2];
 
-    constexpr int PRO = LA < NC ? LA : NC;
-    static_assert(LA <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
+    // chunks 0 .. OWN - 1 (the own rows) come from the previous iteration's epilogue, or on the
+    // first iteration from memory; chunks OWN .. PRO are loaded ahead
+    if (!own_in_lds) {
 #pragma unroll
-    for (int p = 0; p < PRO; ++p) issue(p, p);
-    wait_vm<DPW * (PRO - 1)>();
+      for (int p = 0; p < OWN; ++p) issue(p, p);
+    }
+    constexpr int PRO = OWN + LA - 2 < NC - 1 ? OWN + LA - 2 : NC - 1;
+#pragma unroll
+    for (int p = OWN; p <= PRO; ++p) issue(p, p);
+    wait_vm<DPW * (PRO - OWN + 1)>();
     bare_barrier();
-    load(0);
-    // step st: the spins of step st+1 are read into the other register set while the MFMAs of
-    // step st run. Before the first read of chunk c+1 (in the last step of chunk c) the workgroup
-    // meets at a barrier: chunk c+1 has landed for every wave, and every wave is done reading
-    // chunk c-1, whose buffer then takes chunk c-1+NB.
+#pragma unroll
+    for (int sidx = 0; sidx < D; ++sidx) load(sidx);
+
+    // step sidx (chunk sidx / NST, step sidx % NST): the spins of step sidx + D are read while the
+    // MFMAs of step sidx run. Before the first read of a loaded chunk ci (D steps before it starts)
+    // the workgroup meets at a barrier: chunk ci has landed for every wave, and every wave is done
+    // reading chunk ci - 2 and earlier, so chunk ci + LA - 1 may go to buffer (ci + LA - 1) % NB.
     static_for(
-        [&](auto kc) {
-          constexpr int st = decltype(kc)::value;
-          constexpr int ch = st / KPW;
-          if constexpr (st % KPW == KPW - 1 && ch + 1 < NC) {
-            constexpr int last_issued = (ch + LA - 1 < NC - 1) ? ch + LA - 1 : NC - 1;
-            wait_vm<DPW * (last_issued - (ch + 1))>();
+        [&](auto sc) {
+          constexpr int sidx = decltype(sc)::value;
+          constexpr int i = sidx / NST, st = sidx % NST;
+          constexpr int nxt = sidx + D;
+          if constexpr (nxt < NSTEP && nxt % NST == 0 && nxt / NST >= OWN) {
+            constexpr int ci = nxt / NST;  // chunk about to be read
+            // chunks issued so far: OWN .. PRO, then one per earlier barrier
+            constexpr int issued = (ci + LA - 2 < NC - 1) ? ci + LA - 2 : NC - 1;
+            wait_vm<DPW * (issued - ci)>();
             __builtin_amdgcn_sched_barrier(0);
             bare_barrier();
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (ch + LA < NC) issue(ch + LA, (ch + LA) % NB);
+            if constexpr (ci + LA - 1 < NC) issue(ci + LA - 1, (ci + LA - 1) % NB);
           }
-          wait_lds();
-          if constexpr (st + 1 < KPW * NC) load(st + 1);
-          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (nxt < NSTEP) load(nxt);
 #pragma unroll
-          for (int rt = 0; rt < RTW; ++rt) {
-            const bf16x8 af = fp4x8_to_bf16x8(jr[ch][st % KPW][rt]);
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  af, fb[st & 1][ct], st == 0 ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : acc[rt][ct], 0, 0, 0);
-          }
-          __builtin_amdgcn_sched_barrier(0);
+          for (int at = 0; at < 2; ++at)
+            acc[at] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fp4x8_to_bf16x8(jr[i][st][at]), fb[sidx % (D + 1)],
+                                                             sidx == 0 ? f32x16{} : acc[at], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);  // keeps the reads D steps ahead of their use
         },
-        std::make_integer_sequence<int, KPW * NC>{});
+        std::make_integer_sequence<int, NSTEP>{});
 
     // Lane-dependent values after the k loop are derived afresh from an opaque copy of the lane
-    // index: computed once before the iteration loop they would stay live across the k loop,
-    // where J, the accumulators and the spin fragments need nearly every register.
+    // index, so that they are not kept live across the k loop.
     int lane_e = lane;
     asm volatile("" : "+v"(lane_e));
-    const int c_e = lane_e & 15;
-    const int row0e = rb * XRJ_ROWS + 16 * (RTW * rg + kh) + 4 * (lane_e >> 4);
+    const int c_e = lane_e & 31;
+    const int row0e = rb * XRB_ROWS + 64 * wave + 4 * (lane_e >> 5);
 
-    // ---- the two partial sums of each output --------------------------------------------------
-    // Every wave is past its last read of the ring (the last barrier of the k loop came before the
-    // last chunk's reads, so meet again); then each writes its partial sums of the row tiles the
-    // other waves of its row group own: slot ((rg, kh), j, ct) holds tile j (j-th tile other than kh).
-    bare_barrier();
-    f32x4 own[4];  // selected with compile-time indices (a register array indexed by kh would go to scratch)
+    // the next iteration's temperature (read here, not during the k loop: a scalar load in flight
+    // there would force every LDS wait to wait for all LDS reads); this iteration's 1 / (T_t norm_i)
+    if (t < a.t_end) coef_next = coef[t];
+    f32x4 invc[2][4];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) own[ct] = acc[0][ct];
+    for (int at = 0; at < 2; ++at)
 #pragma unroll
-    for (int qq = 1; qq < RTW; ++qq)
-      if (qq == kh) {
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) own[ct] = acc[qq][ct];
+      for (int j = 0; j < 4; ++j) {
+        const int q = 16 * wave + 8 * at + 2 * j + (lane_e >> 5);
+        invc[at][j] = rowc[0][q] * coef_t;
+        hrow[at][j] = rowc[1][q];
       }
-    f32x4* slots = reinterpret_cast<f32x4*>(smem);
-#pragma unroll
-    for (int rt = 0; rt < RTW; ++rt) {
-      if (rt == kh) continue;
-      const int j = rt < kh ? rt : rt - 1;
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) slots[(((rg * KS + kh) * (KS - 1) + j) * 4 + ct) * 64 + lane_e] = acc[rt][ct];
-    }
-    __syncthreads();
-    f32x4 tot[4];
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      f32x4 sum = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int w = 0; w < KS; ++w) {
-        f32x4 pv;
-        if (w == kh) {
-          pv = own[ct];
-        } else {
-          const int j = kh < w ? kh : kh - 1;
-          pv = slots[(((rg * KS + w) * (KS - 1) + j) * 4 + ct) * 64 + lane_e];
-        }
-        sum = (w == 0) ? pv : sum + pv;  // k half 0, then k half 1
-      }
-      tot[ct] = sum;
-    }
 
     // ---- fused epilogue --------------------------------------------------------------------
-    const float coef_t = coef[t - 1];
+    // The own chunks (buffers 0, 1) were last read at the start of this iteration, so they may be
+    // overwritten without a barrier.
     const int k_rec = t - a.t_begin;
-    // the normalisers of this lane's rows, re-read every iteration (cache hits) rather than held
-    // in registers across the k loop
-    const f32x4 inv = *reinterpret_cast<const f32x4*>(inv_g + row0e);
-    const f32x4 hv = *reinterpret_cast<const f32x4*>(h_g + row0e);
+    {
+      const int r = rgroup0 + c_e;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const int r = rgroup0 + 16 * ct + c_e;
-      __bf16 outv[4];
+      for (int at = 0; at < 2; ++at)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float xf = fmaf(tot[ct][v], inv[v], hv[v]);
-        const float phi = a.negate_noise ? xf - zn[ct][v] : xf + zn[ct][v];
-        const float sh = neg_tanh_from_exp2_arg(phi * coef_t);
-        float sv = fmaf(alpha, sh, oma * s[ct][v]);
-        if (row0e + v >= N) sv = 0.0f;
-        s[ct][v] = sv;
-        outv[v] = (__bf16)sv;
-      }
-      *reinterpret_cast<uint2*>(Snext + (size_t)r * ks + row0e) = *reinterpret_cast<const uint2*>(outv);
-      if (traj && k_rec < a.record && r < a.R) {
+        for (int j = 0; j < 4; ++j) {
+          __bf16 outv[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (row0e + v < N) traj[((size_t)k_rec * a.R + r) * N + row0e + v] = s[ct][v];
+          for (int v = 0; v < 4; ++v) {
+            const int i = 4 * j + v;
+            // -tanh(Phi / T) = 2 / (1 + exp2(arg)) - 1 with arg = 2 log2(e) Phi / T; damped update
+            const float e = __builtin_amdgcn_exp2f(fmaf(acc[at][i], invc[at][j][v], w[at][i]));
+            const float sv = fmaf(alpha2, __builtin_amdgcn_rcpf(1.0f + e), fmaf(oma, s[at][i], nalpha));
+            s[at][i] = sv;
+            outv[v] = (__bf16)sv;
+          }
+          const uint2 pk = *reinterpret_cast<const uint2*>(outv);
+          *reinterpret_cast<uint2*>(Snext + (size_t)r * ks + row0e + 32 * at + 8 * j) = pk;
+          *reinterpret_cast<uint2*>(ring + own_off(at, j, lane_e)) = pk;
+        }
+      if (traj && k_rec < a.record) {
+#pragma unroll
+        for (int at = 0; at < 2; ++at)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int row = row0e + 32 * at + 8 * (i / 4) + i % 4;
+            if (r < a.R && row < N) traj[((size_t)k_rec * a.R + r) * N + row] = s[at][i];
+          }
       }
     }
 
     if (t < a.t_end) {
-      // arrive, draw the next iteration's noise, wait (as in anneal_xrj); the wait ends with a
-      // workgroup barrier, after which the ring (and the partial sums in it) may be overwritten
+      // half of the next iteration's noise while the spin stores complete, arrive (this
+      // workgroup's spins are stored), the other half while the other workgroups arrive, then wait
+      // for the group; the wait ends with a workgroup barrier, after which the ring may be
+      // overwritten
+      draw(t + 1, 0, 4, coef_next);
+      pin_noise(0, 4);
       xcd_group_arrive(bar, xcd_mode, tid);
-      draw_noise_half(t + 1, 0);
-      pin_noise_half(0);
+      draw(t + 1, 4, 2, coef_next);
+      pin_noise(4, 2);
       unsigned seen = 0;
       __builtin_amdgcn_sched_barrier(0);
-      if (tid == 0) seen = ld_dev(bar);
+      if (tid == 0) seen = ld_dev(bar);  // polled once ahead, read after the last draws
       __builtin_amdgcn_sched_barrier(0);
-      draw_noise_half(t + 1, 2);
-      pin_noise_half(2);
+      draw(t + 1, 6, 2, coef_next);
+      pin_noise(6, 2);
       aborted = xrj_group_wait(x, bar, (unsigned)++epoch, xcd_mode, tid, seen, &abort_word);
     }
   }
@@ -790,21 +825,28 @@ __global__ __launch_bounds__(512, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
   // ---- final state and readout ---------------------------------------------------------------
   int lane_f = lane;
   asm volatile("" : "+v"(lane_f));
-  const int row0f = rb * XRJ_ROWS + 16 * (RTW * rg + kh) + 4 * (lane_f >> 4);
+  const int row0f = rb * XRB_ROWS + 64 * wave + 4 * (lane_f >> 5);
+  const int r = rgroup0 + (lane_f & 31);
+  if (r < a.R) {
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int r = rgroup0 + 16 * ct + (lane_f & 15);
-    if (r >= a.R) continue;
+    for (int at = 0; at < 2; ++at)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = row0f + v;
-      if (i < N) {
-        state[(size_t)r * N + i] = s[ct][v];
-        if (a.spins) a.spins[(size_t)r * N + i] = (s[ct][v] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
+      for (int i = 0; i < 16; ++i) {
+        const int row = row0f + 32 * at + 8 * (i / 4) + i % 4;
+        if (row < N) {
+          state[(size_t)r * N + row] = s[at][i];
+          if (a.spins) a.spins[(size_t)r * N + row] = (s[at][i] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
+        }
       }
-    }
   }
 }
+
+// Constants of the FP8-spin register-J kernel below: 128 rows x 64 replicas per workgroup.
+constexpr int XRJ_ROWS = 128;                  // rows of J per workgroup
+constexpr int XRJ_RG = 64;                     // replicas per group
+constexpr int XRJ_KC = 128;                    // k per spin chunk
+constexpr int XRJ_NB = 8;                      // spin chunk buffers in LDS
+constexpr int XRJ_LA = 4;                      // chunks in flight ahead of the one being read
 
 // ---- register-resident J, FP8 spins ----------------------------------------------------------
 // The FP8-spin precision on the same decomposition as anneal_xrj (4 waves per CU, 32 rows of J per
@@ -1081,8 +1123,8 @@ size_t xcd_chunk_bytes() { return (size_t)XCD_RG * XCD_KC * 2; }
 // address bits) was measured to make no difference on MI355X, so the rows are packed.
 int xcd_spin_stride(int Kp) { return Kp; }
 
-int xrj_rows() { return XRJ_ROWS; }
-int xrj_group_replicas() { return XRJ_RG; }
+int xrj_rows(int fp8_spins) { return fp8_spins ? XRJ_ROWS : XRB_ROWS; }
+int xrj_group_replicas(int fp8_spins) { return fp8_spins ? XRJ_RG : XRB_RG; }
 int xrj_kp(int n) { return n <= 512 ? 512 : ((n + 255) / 256) * 256; }
 bool xrj_fits(int n) { return xrj_kp(n) <= 2048; }
 
@@ -1167,7 +1209,7 @@ static const void* xrj_fn(int Kp) {
 hipError_t launch_anneal_xrj(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
   const void* fn = xrj_fn(a.Kp);
   if (!fn) return hipErrorInvalidValue;
-  return launch_resident(fn, groups * x.P, 512, (size_t)XRJ_NB * XRJ_CHB, a, x, st);
+  return launch_resident(fn, groups * x.P, 256, (size_t)XRB_NB * XRB_CHB, a, x, st);
 }
 
 hipError_t launch_anneal_xcd(int jfmt, const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {

@@ -93,9 +93,10 @@ def test_xcd_wider_j_formats(nmfa, kind):
 
 @pytest.mark.parametrize("lds_j", [True, False])
 def test_xcd_local_and_fenced_exchange_agree(nmfa, lds_j):
-    """64 groups over 256 workgroups (LDS-J: P = 4 x 128 replicas; register-J: P = 2 x 64
-    replicas, 128 groups in two launches): every XCD holds whole groups."""
-    inst = instances.gnp(200, 0.3, 5)
+    """Groups spread over several workgroups, so the spins cross workgroups every iteration
+    (LDS-J: n = 200, P = 4 workgroups x 128 replicas, 64 groups; register-J: n = 500, P = 2
+    workgroups x 32 replicas, 256 groups in two launches): every XCD holds whole groups."""
+    inst = instances.gnp(200 if lds_j else 500, 0.3, 5)
     R, t_f = 64 * 128, 300
     out = {}
     for fenced in (False, True):
