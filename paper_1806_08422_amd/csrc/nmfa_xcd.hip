@@ -11,7 +11,7 @@
 //     free. Every format is widened to BF16 in registers for the MFMA.
 //   * S: the operand copy (BF16) of the group's spins lives in global memory, double-buffered by
 //     iteration parity, layout [replica][Kp]. Each iteration the workgroup streams it through
-//     LDS with the direct-to-LDS loads of gfx950 (global_load_lds_dwordx4) in chunks of 64 k
+//     LDS with the direct-to-LDS loads of gfx950 (buffer_load_dwordx4 ... lds) in chunks of 64 k
 //     (16 KB), through a ring of up to 6 buffers (what the LDS beside J allows), so several
 //     chunks are in flight from L2 while the MFMAs consume the oldest one. The fragments of the
 //     next chunk are read from LDS into a second register set while the MFMAs of the current
@@ -365,12 +365,16 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
     __bf16* Snext = (t & 1) ? S0 : S1;
     const __bf16* Sgrp = Scur + (size_t)group * XCD_RG * ks;
 
-    // DMA of chunk ch into buffer buf: DPW wave-instructions of 1 KB per wave
+    // DMA of chunk ch into buffer buf: DPW wave-instructions of 1 KB per wave, through a buffer
+    // resource over the group's spin rows (the global form would make the compiler wait for every
+    // LDS read before each use of one)
+    const __amdgpu_buffer_rsrc_t srs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(Sgrp), 0, XCD_RG * ks * 2, 0x00020000);
     auto issue_chunk = [&](int ch, int buf) {
 #pragma unroll
       for (int u = 0; u < DPW; ++u)
-        __builtin_amdgcn_global_load_lds(Sgrp + dma_src[u] + ch * KC,
-                                         Sl + (size_t)buf * CHUNK_BYTES + dma_dst[u], 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(srs, Sl + (size_t)buf * CHUNK_BYTES + dma_dst[u], 16,
+                                                 (unsigned)dma_src[u] * 2u, ch * KC * 2, 0, 0);
     };
     // this lane's fragments of chunk ch (in buffer buf) into registers
     auto load_frags = [&](AT (&fa)[KSTEPS][2], bf16x8 (&fb)[KSTEPS][2], int ch, int buf) {
