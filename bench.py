@@ -53,17 +53,26 @@ def tts99(t_sample_s: float, p: float) -> float:
     return t_sample_s * math.log(0.01) / math.log(1.0 - p)
 
 
+def kernel_source_sha(kernel_file: str) -> str:
+    """sha256 over a kernel source file followed by the shared device header (Philox, Box-Muller,
+    tanh), the sources a committed counter summary was taken from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in (kernel_file, "nmfa_device.h"):
+        with open(os.path.join(ROOT, "paper_1806_08422_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def measured_traffic(path: str):
     """HBM bytes per launch of the annealing kernel from the committed counter summary, or None
     when the kernel source has changed since the counters were taken (or another path ran)."""
-    import hashlib
-
     prof = os.path.join(ROOT, "profiles", "anneal_xrj_g2000_r1024_tf5000_hbm_bytes.md")
-    src = os.path.join(ROOT, "paper_1806_08422_amd", "csrc", "nmfa_xcd.hip")
     try:
         fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
                       and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "kernel_path"))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_sha("nmfa_xcd.hip")
     except OSError:
         return None
     if fields.get("kernel_source_sha256", "").strip() != sha or fields.get("kernel_path", "").strip() != path:
@@ -74,15 +83,12 @@ def measured_traffic(path: str):
 def measured_busy_xrj(path: str):
     """MFMA and VALU busy fractions of the headline kernel from the committed counter summary, or
     None when the kernel source changed since the counters were taken (or another path ran)."""
-    import hashlib
-
     prof = os.path.join(ROOT, "profiles", "anneal_xrj_g2000_r1024_tf5000_mfma_valu.md")
-    src = os.path.join(ROOT, "paper_1806_08422_amd", "csrc", "nmfa_xcd.hip")
     keys = ("valu_busy_frac", "mfma_busy_frac", "kernel_source_sha256", "kernel_path")
     try:
         fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
                       if ": " in line and line.split(": ", 1)[0] in keys)
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_sha("nmfa_xcd.hip")
     except OSError:
         return None
     if fields.get("kernel_source_sha256", "").strip() != sha or fields.get("kernel_path", "").strip() != path:
@@ -110,15 +116,12 @@ def measured_valu_busy(path: str, profile: str):
     SIMD cycles (over all 1024 SIMDs, while the kernel runs) in which a vector instruction executes,
     from SQ_ACTIVE_INST_VALU (quad-cycles, summed over SIMDs) and GRBM_GUI_ACTIVE. None when the
     kernel source changed since the counters were taken, or another kernel path ran."""
-    import hashlib
-
     prof = os.path.join(ROOT, "profiles", profile)
-    src = os.path.join(ROOT, "paper_1806_08422_amd", "csrc", "nmfa_kernels.hip")
     keys = ("valu_busy_frac", "mfma_busy_frac", "kernel_source_sha256", "kernel_path")
     try:
         fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
                       if ": " in line and line.split(": ", 1)[0] in keys)
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_sha("nmfa_kernels.hip")
     except OSError:
         return None
     if fields.get("kernel_source_sha256", "").strip() != sha or fields.get("kernel_path", "").strip() != path:
