@@ -510,9 +510,12 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
 //     as FP4 (one 32-bit register per 8 couplings: 256 registers at Kp = 2048), so each output's
 //     whole sum stays in one wave. Per 16-k step it widens two J fragments (two 32-row tiles) and
 //     runs two v_mfma_f32_32x32x16_bf16 on the step's spin fragment, read from LDS two steps ahead.
-//   * The group's BF16 spins stream through LDS in 8 KB chunks (32 replicas x 128 k), a ring of
-//     XRB_NB buffers filled XRB_LA chunks ahead by direct-to-LDS buffer loads: a CU receives 128 KB
-//     of spins per iteration.
+//   * The group's BF16 spins stream through LDS in 8 KB chunks (32 replicas x 128 k), one buffer
+//     per chunk, by direct-to-LDS buffer loads: a CU receives 128 KB of spins per iteration. The
+//     loaded chunks come in batches of XRB_GB: the workgroup meets once per batch, when every load
+//     issued so far has landed, and then issues the next batch (fewer barriers, and fewer loads in
+//     flight beside the matrix instructions, measured faster than a barrier per chunk with loads
+//     four chunks ahead).
 //   * The chunks are visited starting at the workgroup's own rows (two chunks) and wrapping around,
 //     the same order on every pass. The spins of the own rows are written into the ring by the
 //     epilogue, so an iteration starts on them while the loads of the other chunks are in flight.
@@ -526,8 +529,8 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
 constexpr int XRB_ROWS = 256;                  // rows of J per workgroup (64 per wave)
 constexpr int XRB_RG = 32;                     // replicas per group
 constexpr int XRB_KC = 128;                    // k per spin chunk
-constexpr int XRB_NB = 16;                     // spin chunk buffers in LDS
-constexpr int XRB_LA = 4;                      // chunks in flight ahead of the one being read
+constexpr int XRB_NB = 16;                     // spin chunk buffers in LDS (one per chunk at Kp = 2048)
+constexpr int XRB_GB = 3;                      // loaded chunks per workgroup barrier (and per batch of loads)
 constexpr int XRB_CHB = XRB_RG * XRB_KC * 2;   // bytes of one chunk: 32 replicas x 128 k, BF16
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -547,11 +550,10 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
   constexpr int NC = NCH, NST = 8, NSTEP = NC * NST;  // chunks; 16-k steps per chunk
   constexpr int D = 2;                                // spin fragments read D steps ahead
   constexpr int OWN = XRB_ROWS / XRB_KC;              // chunks of the workgroup's own rows (2)
-  constexpr int CHB = XRB_CHB, NB = XRB_NB, LA = XRB_LA;
+  constexpr int CHB = XRB_CHB, NB = XRB_NB, GB = XRB_GB;
   constexpr int DPW = CHB / 1024 / 4;                 // 1 KB direct-to-LDS loads per wave and chunk (2)
   static_assert(NC >= OWN + 1 && NC <= NB, "own chunks keep buffers 0 and 1 to themselves");
-  static_assert(DPW * LA <= 63, "wait counts fit the vmcnt field");
-  static_assert(LA <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
+  static_assert(DPW * (OWN + GB) <= 63, "wait counts fit the vmcnt field");
   extern __shared__ __align__(16) unsigned char smem[];  // the chunk ring
   __shared__ unsigned abort_word;                        // the group barrier's decision
   __shared__ f32x4 rowc[2][XRB_ROWS / 4];                // 1 / norm_i and h_i / norm_i of the workgroup's rows
@@ -698,9 +700,14 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
     auto issue = [&](int i, int buf) {
       int ch = OWN * rb_t + i;
       if (ch >= NC) ch -= NC;
+      // the LDS destination is formed at each issue from an opaque copy of the wave's base: every
+      // (buffer, load) address held across the loop would take a scalar register, and the
+      // compiler spills scalar registers to vector lanes beyond about a hundred of them
+      int wb = DPW * 1024 * wave;
+      asm volatile("" : "+s"(wb));
 #pragma unroll
       for (int u = 0; u < DPW; ++u)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(srs, ring + buf * CHB + (DPW * wave + u) * 1024, 16, dma_off[u],
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(srs, ring + wb + buf * CHB + u * 1024, 16, dma_off[u],
                                                  ch * 2 * XRB_KC, 0, 0);
     };
     bf16x8 fb[D + 1];  // [register set]: the spins of one 16-k step
@@ -710,12 +717,14 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
     f32x16 acc[2];
 
     // chunks 0 .. OWN - 1 (the own rows) come from the previous iteration's epilogue, or on the
-    // first iteration from memory; chunks OWN .. PRO are loaded ahead
+    // first iteration from memory; the first batch, chunks OWN .. PRO, is loaded while they are
+    // multiplied. Chunk ch always goes to buffer ch (NC <= NB): the group barrier at the end of the
+    // previous iteration orders every load after every read of the buffer it overwrites.
     if (!own_in_lds) {
 #pragma unroll
       for (int p = 0; p < OWN; ++p) issue(p, p);
     }
-    constexpr int PRO = OWN + LA - 2 < NC - 1 ? OWN + LA - 2 : NC - 1;
+    constexpr int PRO = OWN + GB - 1 < NC - 1 ? OWN + GB - 1 : NC - 1;
 #pragma unroll
     for (int p = OWN; p <= PRO; ++p) issue(p, p);
     wait_vm<DPW * (PRO - OWN + 1)>();
@@ -724,23 +733,22 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
     for (int sidx = 0; sidx < D; ++sidx) load(sidx);
 
     // step sidx (chunk sidx / NST, step sidx % NST): the spins of step sidx + D are read while the
-    // MFMAs of step sidx run. Before the first read of a loaded chunk ci (D steps before it starts)
-    // the workgroup meets at a barrier: chunk ci has landed for every wave, and every wave is done
-    // reading chunk ci - 2 and earlier, so chunk ci + LA - 1 may go to buffer (ci + LA - 1) % NB.
+    // MFMAs of step sidx run. Before the first read of the batch that starts at chunk ci (D steps
+    // before it starts) every wave waits for all of its loads and the workgroup meets at a
+    // barrier: chunks ci .. ci + GB - 1 have landed for every wave. The next batch is issued then.
     static_for(
         [&](auto sc) {
           constexpr int sidx = decltype(sc)::value;
           constexpr int i = sidx / NST, st = sidx % NST;
           constexpr int nxt = sidx + D;
-          if constexpr (nxt < NSTEP && nxt % NST == 0 && nxt / NST >= OWN) {
-            constexpr int ci = nxt / NST;  // chunk about to be read
-            // chunks issued so far: OWN .. PRO, then one per earlier barrier
-            constexpr int issued = (ci + LA - 2 < NC - 1) ? ci + LA - 2 : NC - 1;
-            wait_vm<DPW * (issued - ci)>();
+          if constexpr (nxt < NSTEP && nxt % NST == 0 && nxt / NST >= OWN && (nxt / NST - OWN) % GB == 0) {
+            constexpr int ci = nxt / NST;  // first chunk of the batch about to be read
+            wait_vm<0>();
             __builtin_amdgcn_sched_barrier(0);
             bare_barrier();
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (ci + LA - 1 < NC) issue(ci + LA - 1, (ci + LA - 1) % NB);
+#pragma unroll
+            for (int q = ci + GB; q < ci + 2 * GB && q < NC; ++q) issue(q, q);
           }
           if constexpr (nxt < NSTEP) load(nxt);
 #pragma unroll
@@ -850,7 +858,7 @@ constexpr int XRJ_ROWS = 128;                  // rows of J per workgroup
 constexpr int XRJ_RG = 64;                     // replicas per group
 constexpr int XRJ_KC = 128;                    // k per spin chunk
 constexpr int XRJ_NB = 8;                      // spin chunk buffers in LDS
-constexpr int XRJ_LA = 4;                      // chunks in flight ahead of the one being read
+constexpr int XRJ_GB = 3;                      // chunks per workgroup barrier (and per batch of loads)
 
 // ---- register-resident J, FP8 spins ----------------------------------------------------------
 // The FP8-spin precision on the same decomposition as anneal_xrj (4 waves per CU, 32 rows of J per
@@ -876,8 +884,9 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj8(AnnealArgs a, XcdArgs x) {
   constexpr int NB = XRJ_NB;
   constexpr int RT = 2;
   constexpr int DPW = 2;  // 1 KB direct-to-LDS loads per wave and chunk (8 KB over 4 waves)
-  static_assert(DPW * (XRJ_LA - 1) <= 63, "wait counts fit the vmcnt field");
-  static_assert(XRJ_LA <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
+  constexpr int GB = XRJ_GB;
+  static_assert(DPW * (GB + 1) <= 63, "wait counts fit the vmcnt field");
+  static_assert(2 * GB <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
   const int N = a.N, ks = x.ks;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g4 = lane >> 4, c = lane & 15;
@@ -990,10 +999,13 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj8(AnnealArgs a, XcdArgs x) {
     unsigned char* Snext = const_cast<unsigned char*>((t & 1) ? S0 : S1);
 
     auto issue = [&](int ch, int buf) {
+      // LDS destination from an opaque copy of the wave's base (no scalar register per address)
+      int wb = __builtin_amdgcn_readfirstlane(DPW * 1024 * wave);
+      asm volatile("" : "+s"(wb));
 #pragma unroll
       for (int u = 0; u < DPW; ++u)
         __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(Sg + dma_off[u] + ch * XRJ_KC),
-                                         ring + buf * XRJ8_CHB + (DPW * wave + u) * 1024, 16, 0, 0);
+                                         ring + wb + buf * XRJ8_CHB + u * 1024, 16, 0, 0);
     };
     i32x8 fb[2][4];  // [register set][column tile]: the spins of one 128-k chunk
     auto load = [&](int ch) {
@@ -1013,26 +1025,29 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj8(AnnealArgs a, XcdArgs x) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
 
-    constexpr int PRO = XRJ_LA < NCH ? XRJ_LA : NCH;
+    // Chunks come in batches of GB: the spins of chunk ch + 1 are read into the other register set
+    // while the MFMAs of chunk ch run, so the batch of steps ch .. ch + GB - 1 reads chunks
+    // ch + 1 .. ch + GB. Chunks 0 .. GB are loaded before the first step and the batch after them
+    // at once; at step ch = m GB (m >= 1) every wave waits for all of its loads (chunks up to
+    // ch + GB), the workgroup meets, and chunks ch + GB + 1 .. ch + 2 GB are issued into buffers
+    // last used by chunks up to ch + 2 GB - NB <= ch - 1, whose reads every wave has waited for.
 #pragma unroll
-    for (int q = 0; q < PRO; ++q) issue(q, q);
-    wait_vm<DPW * (PRO - 1)>();
+    for (int q = 0; q <= GB && q < NCH; ++q) issue(q, q);
+    wait_vm<0>();
     bare_barrier();
+#pragma unroll
+    for (int q = GB + 1; q <= 2 * GB && q < NCH; ++q) issue(q, q % NB);
     load(0);
-    // chunk ch: chunk ch+1 has landed for every wave once they meet at the barrier (and every
-    // wave is done with chunk ch-1); its spins are read into the other register set while the
-    // MFMAs of chunk ch run; chunk ch+XRJ_LA goes to buffer (ch+XRJ_LA) % NB, last used by chunk
-    // ch+XRJ_LA-NB <= ch-1
     static_for(
         [&](auto chc) {
           constexpr int ch = decltype(chc)::value;
-          if constexpr (ch + 1 < NCH) {
-            constexpr int last_issued = (ch + XRJ_LA - 1 < NCH - 1) ? ch + XRJ_LA - 1 : NCH - 1;
-            wait_vm<DPW * (last_issued - (ch + 1))>();
+          if constexpr (ch + 1 < NCH && ch > 0 && ch % GB == 0) {
+            wait_vm<0>();
             __builtin_amdgcn_sched_barrier(0);
             bare_barrier();
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (ch + XRJ_LA < NCH) issue(ch + XRJ_LA, (ch + XRJ_LA) % NB);
+#pragma unroll
+            for (int q = ch + GB + 1; q <= ch + 2 * GB && q < NCH; ++q) issue(q, q % NB);
           }
           wait_lds();
           if constexpr (ch + 1 < NCH) load(ch + 1);
