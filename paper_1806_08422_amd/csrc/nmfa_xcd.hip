@@ -509,7 +509,7 @@ __global__ __launch_bounds__(512, 1) void anneal_xcd(AnnealArgs a, XcdArgs x) {
 //   * Wave w keeps rows 64 w .. 64 w + 63 of the workgroup's block of J for every k in registers,
 //     as FP4 (one 32-bit register per 8 couplings: 256 registers at Kp = 2048), so each output's
 //     whole sum stays in one wave. Per 16-k step it widens two J fragments (two 32-row tiles) and
-//     runs two v_mfma_f32_32x32x16_bf16 on the step's spin fragment, read from LDS two steps ahead.
+//     runs two v_mfma_f32_32x32x16_bf16 on the step's spin fragment, read from LDS three steps ahead.
 //   * The group's BF16 spins stream through LDS in 8 KB chunks (32 replicas x 128 k), one buffer
 //     per chunk, by direct-to-LDS buffer loads: a CU receives 128 KB of spins per iteration. The
 //     loaded chunks come in batches of XRB_GB: the workgroup meets once per batch, when every load
@@ -548,7 +548,7 @@ __device__ __forceinline__ void static_for(F&& f, std::integer_sequence<int, I..
 template <int NCH>
 __global__ __launch_bounds__(256, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
   constexpr int NC = NCH, NST = 8, NSTEP = NC * NST;  // chunks; 16-k steps per chunk
-  constexpr int D = 2;                                // spin fragments read D steps ahead
+  constexpr int D = 3;                                // spin fragments read D steps ahead
   constexpr int OWN = XRB_ROWS / XRB_KC;              // chunks of the workgroup's own rows (2)
   constexpr int CHB = XRB_CHB, NB = XRB_NB, GB = XRB_GB;
   constexpr int DPW = CHB / 1024 / 4;                 // 1 KB direct-to-LDS loads per wave and chunk (2)
