@@ -853,43 +853,51 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
   }
 }
 
-// Constants of the FP8-spin register-J kernel below: 128 rows x 64 replicas per workgroup.
-constexpr int XRJ_ROWS = 128;                  // rows of J per workgroup
-constexpr int XRJ_RG = 64;                     // replicas per group
-constexpr int XRJ_KC = 128;                    // k per spin chunk
-constexpr int XRJ_NB = 8;                      // spin chunk buffers in LDS
-constexpr int XRJ_GB = 3;                      // chunks per workgroup barrier (and per batch of loads)
-
 // ---- register-resident J, FP8 spins ----------------------------------------------------------
-// The FP8-spin precision on the same decomposition as anneal_xrj (4 waves per CU, 32 rows of J per
-// wave in FP4 registers, groups of 64 replicas): the mean field runs on the mixed-format matrix
-// instruction v_mfma_scale_f32_16x16x128_f8f6f4 with the FP4 couplings as A operand and the FP8
-// E4M3 spins as B operand, both taken as they are stored (unit scales). The two operands lay out
-// k differently (measured on gfx950 with a one-hot probe): lane 16 g + i of the FP4 operand holds
-// row i at k = 32 g .. 32 g + 31 of the 128-k step (nibbles low first), which is how the J
-// registers are laid out, so J needs no widening; lane 16 g + i of the FP8 operand holds column i
-// at k = 16 g .. 16 g + 15 in its first 16 bytes and at k = 64 + 16 g .. 64 + 16 g + 15 in its
-// last 16. One 128-k chunk is one MFMA per (row tile, column tile). Spin chunks are 64 replicas x
-// 128 bytes (8 KB); unit u (16 k) of replica q is stored at u ^ ((q >> 1) & 7) of its 128-byte
-// row, so that the 16 lanes a ds_read_b128 serves hit 16 distinct 16-byte bank groups. The
-// epilogue packs each lane's four new spins of a column tile into one 32-bit word.
-constexpr int XRJ8_CHB = XRJ_RG * XRJ_KC;  // bytes of one chunk: 64 replicas x 128 k, FP8
+// The FP8-spin precision on the decomposition of anneal_xrj (256 rows x 32 replicas per
+// workgroup, four waves of 64 rows each with every k of FP4 J in registers, groups of 32
+// replicas): the mean field runs on the mixed-format matrix instruction
+// v_mfma_scale_f32_16x16x128_f8f6f4 with the FP4 couplings as A operand and the FP8 E4M3 spins as
+// B operand, both taken as they are stored (unit scales), so J needs no widening. The two operands
+// lay out k differently (measured on gfx950 with a one-hot probe): lane 16 g + i of the FP4
+// operand holds row i at k = 32 g .. 32 g + 31 of the 128-k step (nibbles low first), which is how
+// the J registers are laid out; lane 16 g + i of the FP8 operand holds column i at
+// k = 16 g .. 16 g + 15 in its first 16 bytes and at k = 64 + 16 g .. 64 + 16 g + 15 in its last
+// 16. One 128-k chunk is one MFMA per (16-row tile, 16-column tile): 4 x 2 per wave.
+//   * Spin chunks are 32 replicas x 128 bytes (4 KB); unit u (16 k) of replica q is stored at
+//     u ^ ((q >> 1) & 7) of its 128-byte row, so the 16 lanes a ds_read_b128 serves hit 16
+//     distinct 16-byte bank groups. A CU receives 64 KB of spins per iteration, one buffer per
+//     chunk, loaded by direct-to-LDS buffer loads in batches of XR8_GB chunks (one workgroup
+//     barrier per batch, as in anneal_xrj).
+//   * The chunks are visited from the workgroup's own rows (two chunks), which the epilogue writes
+//     into buffers 0 and 1 as well as to memory; the fragments of the next chunk are read into a
+//     second register set while the MFMAs of the current one run.
+//   * The Philox noise of the next iteration and its field term are drawn while the group barrier
+//     completes; the per-row constants live in LDS; the epilogue (exp2, reciprocal, damped update)
+//     packs each lane's four new spins of a (row tile, column tile) into one 32-bit word.
+constexpr int XR8_ROWS = 256;                  // rows of J per workgroup (64 per wave)
+constexpr int XR8_RG = 32;                     // replicas per group
+constexpr int XR8_KC = 128;                    // k per spin chunk
+constexpr int XR8_NB = 16;                     // spin chunk buffers in LDS (one per chunk at Kp = 2048)
+constexpr int XR8_GB = 3;                      // loaded chunks per workgroup barrier (and per batch of loads)
+constexpr int XR8_CHB = XR8_RG * XR8_KC;       // bytes of one chunk: 32 replicas x 128 k, FP8
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 template <int NCH>
 __global__ __launch_bounds__(256, 1) void anneal_xrj8(AnnealArgs a, XcdArgs x) {
-  extern __shared__ __align__(16) unsigned char smem[];  // XRJ_NB chunk buffers
+  constexpr int NC = NCH, RT = 4, CT = 2;
+  constexpr int OWN = XR8_ROWS / XR8_KC;  // chunks of the workgroup's own rows (2)
+  constexpr int CHB = XR8_CHB, NB = XR8_NB, GB = XR8_GB;
+  static_assert(NC >= OWN + 1 && NC <= NB, "own chunks keep buffers 0 and 1 to themselves");
+  static_assert(OWN + GB <= 63, "wait counts fit the vmcnt field");
+  extern __shared__ __align__(16) unsigned char smem[];  // the chunk buffers
   __shared__ unsigned abort_word;                        // the group barrier's decision
-  constexpr int NB = XRJ_NB;
-  constexpr int RT = 2;
-  constexpr int DPW = 2;  // 1 KB direct-to-LDS loads per wave and chunk (8 KB over 4 waves)
-  constexpr int GB = XRJ_GB;
-  static_assert(DPW * (GB + 1) <= 63, "wait counts fit the vmcnt field");
-  static_assert(2 * GB <= NB - 1, "a chunk may only be loaded into a buffer that every wave is done with");
+  __shared__ f32x4 rowc[2][XR8_ROWS / 4];                // 1 / norm_i and h_i / norm_i of the workgroup's rows
   const int N = a.N, ks = x.ks;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g4 = lane >> 4, c = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar registers
+  const int g = lane >> 4, c = lane & 15;
 
   const XcdSlot slot = xcd_register(x, tid);
   const unsigned my_group = slot.my_group;
@@ -898,94 +906,105 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj8(AnnealArgs a, XcdArgs x) {
   const bool xcd_mode = slot.xcd_mode;
   bool aborted = slot.aborted;
 
-  // J of this wave, as in anneal_xrj: jr[ch][q][rt] = the 8 FP4 couplings of row
-  // rb*128 + 32*wave + 16*rt + c at k = 128*ch + 32*g4 + 8*q .. +7
-  uint32_t jr[NCH][4][RT];
+  // J of this wave: jr[i][rt][q] = the 8 FP4 couplings of row rb*256 + 64 wave + 16 rt + c at
+  // k = 128 ch + 32 g + 8 q .. +7 with ch = (2 rb + i) mod NC
+  uint32_t jr[NC][RT][4];
   {
-    const int jrow = 64 * NCH;  // bytes of one FP4 row (Kp / 2)
+    const int jrow = 64 * NC;  // bytes of one FP4 row (Kp / 2)
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       const unsigned char* p = reinterpret_cast<const unsigned char*>(a.J) +
-                               (size_t)(rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + c) * jrow + 16 * g4;
+                               (size_t)(rb * XR8_ROWS + 64 * wave + 16 * rt + c) * jrow + 16 * g;
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) {
+      for (int i = 0; i < NC; ++i) {
+        const int ch = (OWN * rb + i) % NC;
         const uint4 v = *reinterpret_cast<const uint4*>(p + 64 * ch);
-        jr[ch][0][rt] = v.x;
-        jr[ch][1][rt] = v.y;
-        jr[ch][2][rt] = v.z;
-        jr[ch][3][rt] = v.w;
+        jr[i][rt][0] = v.x;
+        jr[i][rt][1] = v.y;
+        jr[i][rt][2] = v.z;
+        jr[i][rt][3] = v.w;
       }
     }
   }
 
-  const float* inv_g = reinterpret_cast<const float*>(a.inv_norm);
-  const float* h_g = reinterpret_cast<const float*>(a.hterm);
+  if (tid < XR8_ROWS / 4) {
+    rowc[0][tid] = reinterpret_cast<const f32x4*>(a.inv_norm)[rb * (XR8_ROWS / 4) + tid];
+    rowc[1][tid] = reinterpret_cast<const f32x4*>(a.hterm)[rb * (XR8_ROWS / 4) + tid];
+  }
+  __syncthreads();
   float* state = reinterpret_cast<float*>(a.state);
   float* traj = reinterpret_cast<float*>(a.traj);
   const float* coef = reinterpret_cast<const float*>(a.coef);
-  float inv[RT][4], hv[RT][4], s[RT][4][4];
-  int row0[RT];
+  // outputs of this lane: rows row0 + 16 rt + v (rt, v = 0..3), replicas rgroup0 + 16 ct + c
+  const int row0 = rb * XR8_ROWS + 64 * wave + 4 * g;
+  const int rgroup0 = group * XR8_RG;
+  float s[RT][CT][4];
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    row0[rt] = rb * XRJ_ROWS + 16 * RT * wave + 16 * rt + 4 * g4;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      inv[rt][v] = inv_g[row0[rt] + v];
-      hv[rt][v] = h_g[row0[rt] + v];
-    }
-  }
-  const int rgroup0 = group * XRJ_RG;
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
+  for (int ct = 0; ct < CT; ++ct) {
     const int r = rgroup0 + 16 * ct + c;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = row0[rt] + v;
-        s[rt][ct][v] = (a.load_state && r < a.R && i < N) ? state[(size_t)r * N + i] : 0.0f;
+        const int row = row0 + 16 * rt + v;
+        s[rt][ct][v] = (a.load_state && r < a.R && row < N) ? state[(size_t)r * N + row] : 0.0f;
       }
   }
   const float sg = (float)a.sigma;
   const float neg2ln2_s2 = -2.0f * 0.6931471805599453f * sg * sg;
-  const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha);
-  float zn[RT][4][4];
-  auto draw_noise_half = [&](int tt, int ct0) {
-#pragma unroll
-    for (int ct = ct0; ct < ct0 + 2; ++ct)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-        sigma_gauss4_f32(philox4x32_10((uint32_t)(row0[rt] >> 2), (uint32_t)(rgroup0 + 16 * ct + c), (uint32_t)tt, 0u,
-                                       a.key0, a.key1),
-                         neg2ln2_s2, zn[rt][ct]);
-  };
-  auto pin_noise_half = [&](int ct0) {
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int ct = ct0; ct < ct0 + 2; ++ct)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(zn[rt][ct][v]));
-  };
-  draw_noise_half(a.t_begin, 0);
-  draw_noise_half(a.t_begin, 2);
+  const float alpha2 = (float)(2.0 * a.alpha), nalpha = (float)(-a.alpha), oma = (float)(1.0 - a.alpha);
 
-  // spin fragments: lane (c, g4) of column tile ct reads units g4 and g4 + 4 of replica 16*ct + c
+  // spin fragments: lane (c, g) of column tile ct reads units g and g + 4 of replica 16 ct + c
   // (the FP8 operand's k layout); (q >> 1) & 7 does not depend on ct, and the column tiles are
   // 2 KB apart
   int boff[2];
 #pragma unroll
-  for (int hf = 0; hf < 2; ++hf) boff[hf] = c * 128 + ((g4 + 4 * hf) ^ ((c >> 1) & 7)) * 16;
-  // direct-to-LDS loads: block b (1 KB) holds replicas 8b .. 8b + 7; lane l fills position l % 8
-  // of replica 8b + l / 8 with the global unit that the swizzle puts there
-  unsigned dma_off[DPW];
-#pragma unroll
-  for (int u = 0; u < DPW; ++u) {
-    const int blk = DPW * wave + u;
-    const int q = 8 * blk + (lane >> 3);
+  for (int hf = 0; hf < 2; ++hf) boff[hf] = c * 128 + (((g + 4 * hf) ^ ((c >> 1) & 7)) * 16);
+  // direct-to-LDS loads: a chunk is 4 loads of 1 KB, wave w fills replicas 8 w .. 8 w + 7; lane l
+  // fills position l % 8 of replica 8 w + l / 8 with the global unit the swizzle puts there
+  unsigned dma_off;
+  {
+    const int q = 8 * wave + (lane >> 3);
     const int pos = lane & 7;
-    dma_off[u] = (unsigned)(q * ks + (pos ^ ((q >> 1) & 7)) * 16);  // bytes within the group's block
+    dma_off = (unsigned)(q * ks + (pos ^ ((q >> 1) & 7)) * 16);
   }
+  // where this lane's four new spins of tile (rt, ct) go in the own chunks (buffers 0, 1):
+  // workgroup row 64 wave + 16 rt + 4 g is k = 64 (wave & 1) + 16 rt + 4 g of own chunk wave / 2,
+  // i.e. bytes 4 g .. 4 g + 3 of unit 4 (wave & 1) + rt
+  auto own_off = [&](int rt, int ct, int ln) {
+    const int q = 16 * ct + (ln & 15);
+    return (wave >> 1) * CHB + q * 128 + (((4 * (wave & 1) + rt) ^ ((q >> 1) & 7)) * 16) + 4 * (ln >> 4);
+  };
+
+  // w = (h_i + sigma z) / (T_t norm_i) for this lane's outputs of iteration tt (exp2 units), with the
+  // Philox noise of (row quad, replica, tt); draw d covers tile (d / 2, d % 2). Drawn one iteration
+  // ahead, while the group barrier of the previous iteration completes.
+  float w[RT][CT][4];
+  float coef_next = coef[a.t_begin - 1];
+  f32x4 hrow[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) hrow[rt] = rowc[1][16 * wave + 4 * rt + g];
+  auto draw = [&](int tt, int d0, int nd, float coef_tt) {
+    const float coef_z = a.negate_noise ? -coef_tt : coef_tt;
+#pragma unroll
+    for (int d = d0; d < d0 + nd; ++d) {
+      const int rt = d >> 1, ct = d & 1;
+      float z[4];
+      sigma_gauss4_f32(philox4x32_10((uint32_t)((row0 + 16 * rt) >> 2), (uint32_t)(rgroup0 + 16 * ct + c),
+                                     (uint32_t)tt, 0u, a.key0, a.key1),
+                       neg2ln2_s2, z);
+      const f32x4 hc = hrow[rt] * coef_tt;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) w[rt][ct][v] = fmaf(z[v], coef_z, hc[v]);
+    }
+  };
+  auto pin_noise = [&](int d0, int nd) {
+#pragma unroll
+    for (int d = d0; d < d0 + nd; ++d)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(w[d >> 1][d & 1][v]));
+  };
+  draw(a.t_begin, 0, 8, coef_next);
 
   const unsigned char* S0 = reinterpret_cast<const unsigned char*>(x.S[0]);
   const unsigned char* S1 = reinterpret_cast<const unsigned char*>(x.S[1]);
@@ -995,139 +1014,171 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj8(AnnealArgs a, XcdArgs x) {
   __syncthreads();
 
   for (int t = a.t_begin; t <= a.t_end && !aborted; ++t) {
-    const unsigned char* Sg = ((t & 1) ? S1 : S0) + (size_t)group * XRJ_RG * ks;
+    const float coef_t = coef_next;
+    const unsigned char* Sg = ((t & 1) ? S1 : S0) + (size_t)group * XR8_RG * ks;
     unsigned char* Snext = const_cast<unsigned char*>((t & 1) ? S0 : S1);
+    const bool own_in_lds = t > a.t_begin;
 
-    auto issue = [&](int ch, int buf) {
-      // LDS destination from an opaque copy of the wave's base (no scalar register per address)
-      int wb = __builtin_amdgcn_readfirstlane(DPW * 1024 * wave);
+    int rb_t = rb;
+    asm volatile("" : "+s"(rb_t));
+    const __amdgpu_buffer_rsrc_t srs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(Sg), 0, XR8_RG * ks, 0x00020000);
+    auto issue = [&](int i, int buf) {
+      int ch = OWN * rb_t + i;
+      if (ch >= NC) ch -= NC;
+      int wb = 1024 * wave;  // LDS destination from an opaque per-wave base (no scalar register per address)
       asm volatile("" : "+s"(wb));
-#pragma unroll
-      for (int u = 0; u < DPW; ++u)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(Sg + dma_off[u] + ch * XRJ_KC),
-                                         ring + wb + buf * XRJ8_CHB + u * 1024, 16, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(srs, ring + wb + buf * CHB, 16, dma_off, ch * XR8_KC, 0, 0);
     };
-    i32x8 fb[2][4];  // [register set][column tile]: the spins of one 128-k chunk
-    auto load = [&](int ch) {
+    i32x8 fb[2][CT];  // [register set][column tile]: the spins of one 128-k chunk
+    auto load = [&](int i) {
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const unsigned char* base = smem + (ch % NB) * XRJ8_CHB + 2048 * ct;
+      for (int ct = 0; ct < CT; ++ct) {
+        const unsigned char* base = smem + i * CHB + 2048 * ct;
         const uint4 lo = *reinterpret_cast<const uint4*>(base + boff[0]);
         const uint4 hi = *reinterpret_cast<const uint4*>(base + boff[1]);
-        fb[ch & 1][ct] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        fb[i & 1][ct] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
       }
     };
-    f32x4 acc[RT][4];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
+    f32x4 acc[RT][CT];
 
-    // Chunks come in batches of GB: the spins of chunk ch + 1 are read into the other register set
-    // while the MFMAs of chunk ch run, so the batch of steps ch .. ch + GB - 1 reads chunks
-    // ch + 1 .. ch + GB. Chunks 0 .. GB are loaded before the first step and the batch after them
-    // at once; at step ch = m GB (m >= 1) every wave waits for all of its loads (chunks up to
-    // ch + GB), the workgroup meets, and chunks ch + GB + 1 .. ch + 2 GB are issued into buffers
-    // last used by chunks up to ch + 2 GB - NB <= ch - 1, whose reads every wave has waited for.
+    // chunks 0 .. OWN - 1 (the own rows) come from the previous iteration's epilogue, or on the
+    // first iteration from memory; the first batch, chunks OWN .. PRO, is loaded while they are
+    // multiplied. Chunk i always goes to buffer i (NC <= NB): the group barrier at the end of the
+    // previous iteration orders every load after every read of the buffer it overwrites.
+    if (!own_in_lds) {
 #pragma unroll
-    for (int q = 0; q <= GB && q < NCH; ++q) issue(q, q);
-    wait_vm<0>();
+      for (int p = 0; p < OWN; ++p) issue(p, p);
+    }
+    constexpr int PRO = OWN + GB - 1 < NC - 1 ? OWN + GB - 1 : NC - 1;
+#pragma unroll
+    for (int p = OWN; p <= PRO; ++p) issue(p, p);
+    wait_vm<PRO - OWN + 1>();
     bare_barrier();
-#pragma unroll
-    for (int q = GB + 1; q <= 2 * GB && q < NCH; ++q) issue(q, q % NB);
     load(0);
+
+    // chunk i: the spins of chunk i + 1 are read into the other register set while the MFMAs of
+    // chunk i run. Before the first read of the batch that starts at chunk ci (during chunk ci - 1)
+    // every wave waits for all of its loads and the workgroup meets at a barrier: chunks
+    // ci .. ci + GB - 1 have landed for every wave. The next batch is issued then.
     static_for(
-        [&](auto chc) {
-          constexpr int ch = decltype(chc)::value;
-          if constexpr (ch + 1 < NCH && ch > 0 && ch % GB == 0) {
+        [&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          constexpr int ci = i + 1;
+          if constexpr (ci < NC && ci >= OWN && (ci - OWN) % GB == 0) {
             wait_vm<0>();
             __builtin_amdgcn_sched_barrier(0);
             bare_barrier();
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int q = ch + GB + 1; q <= ch + 2 * GB && q < NCH; ++q) issue(q, q % NB);
+            for (int q = ci + GB; q < ci + 2 * GB && q < NC; ++q) issue(q, q);
           }
           wait_lds();
-          if constexpr (ch + 1 < NCH) load(ch + 1);
+          if constexpr (i + 1 < NC) load(i + 1);
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt) {
-            const i32x8 af = i32x8{(int)jr[ch][0][rt], (int)jr[ch][1][rt], (int)jr[ch][2][rt], (int)jr[ch][3][rt],
+            const i32x8 af = i32x8{(int)jr[i][rt][0], (int)jr[i][rt][1], (int)jr[i][rt][2], (int)jr[i][rt][3],
                                    0, 0, 0, 0};
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-              acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af, fb[ch & 1][ct], acc[rt][ct], 4, 0, 0,
-                                                                              0x7f7f7f7f, 0, 0x7f7f7f7f);
+            for (int ct = 0; ct < CT; ++ct)
+              acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                  af, fb[i & 1][ct], i == 0 ? f32x4{} : acc[rt][ct], 4, 0, 0, 0x7f7f7f7f, 0, 0x7f7f7f7f);
           }
-          // The MFMA builtin has no side effects, so without this the compiler sinks every chunk's
-          // MFMAs to the epilogue and keeps all chunks' spin fragments live: an empty volatile
-          // statement that takes the accumulators (in the accumulation registers) holds each
-          // chunk's MFMAs in its own step.
+          // The MFMA builtin has no side effects: without this the compiler sinks every chunk's
+          // MFMAs to the epilogue and keeps all chunks' spin fragments live.
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) asm volatile("" : "+a"(acc[rt][ct]));
+            for (int ct = 0; ct < CT; ++ct) asm volatile("" : "+a"(acc[rt][ct]));
           __builtin_amdgcn_sched_barrier(0);
         },
-        std::make_integer_sequence<int, NCH>{});
+        std::make_integer_sequence<int, NC>{});
+
+    int lane_e = lane;
+    asm volatile("" : "+v"(lane_e));
+    const int c_e = lane_e & 15;
+    const int row0e = rb * XR8_ROWS + 64 * wave + 4 * (lane_e >> 4);
+
+    if (t < a.t_end) coef_next = coef[t];
+    f32x4 invc[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int q = 16 * wave + 4 * rt + (lane_e >> 4);
+      invc[rt] = rowc[0][q] * coef_t;
+      hrow[rt] = rowc[1][q];
+    }
 
     // ---- fused epilogue --------------------------------------------------------------------
-    const float coef_t = coef[t - 1];
+    // The own chunks (buffers 0, 1) were last read at the start of this iteration, so they may be
+    // overwritten without a barrier.
     const int k_rec = t - a.t_begin;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const int r = rgroup0 + 16 * ct + c;
+    for (int ct = 0; ct < CT; ++ct) {
+      const int r = rgroup0 + 16 * ct + c_e;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float xf = fmaf(acc[rt][ct][v], inv[rt][v], hv[rt][v]);
-          const float phi = a.negate_noise ? xf - zn[rt][ct][v] : xf + zn[rt][ct][v];
-          const float sh = neg_tanh_from_exp2_arg(phi * coef_t);
-          float sv = fmaf(alpha, sh, oma * s[rt][ct][v]);
-          if (row0[rt] + v >= N) sv = 0.0f;
-          s[rt][ct][v] = sv;
+          // -tanh(Phi / T) = 2 / (1 + exp2(arg)) - 1 with arg = 2 log2(e) Phi / T; damped update
+          const float e = __builtin_amdgcn_exp2f(fmaf(acc[rt][ct][v], invc[rt][v], w[rt][ct][v]));
+          s[rt][ct][v] = fmaf(alpha2, __builtin_amdgcn_rcpf(1.0f + e), fmaf(oma, s[rt][ct][v], nalpha));
         }
-        int w = __builtin_amdgcn_cvt_pk_fp8_f32(s[rt][ct][0], s[rt][ct][1], 0, false);
-        w = __builtin_amdgcn_cvt_pk_fp8_f32(s[rt][ct][2], s[rt][ct][3], w, true);
-        *reinterpret_cast<int*>(Snext + (size_t)r * ks + row0[rt]) = w;
-        if (traj && k_rec < a.record && r < a.R) {
+        int pk = __builtin_amdgcn_cvt_pk_fp8_f32(s[rt][ct][0], s[rt][ct][1], 0, false);
+        pk = __builtin_amdgcn_cvt_pk_fp8_f32(s[rt][ct][2], s[rt][ct][3], pk, true);
+        *reinterpret_cast<int*>(Snext + (size_t)r * ks + row0e + 16 * rt) = pk;
+        *reinterpret_cast<int*>(ring + own_off(rt, ct, lane_e)) = pk;
+      }
+    }
+    if (traj && k_rec < a.record) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (row0[rt] + v < N) traj[((size_t)k_rec * a.R + r) * N + row0[rt] + v] = s[rt][ct][v];
-        }
+      for (int ct = 0; ct < CT; ++ct) {
+        const int r = rgroup0 + 16 * ct + c_e;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = row0e + 16 * rt + v;
+            if (r < a.R && row < N) traj[((size_t)k_rec * a.R + r) * N + row] = s[rt][ct][v];
+          }
       }
     }
 
     if (t < a.t_end) {
+      // half of the next iteration's noise while the spin stores complete, arrive, the other half
+      // while the other workgroups arrive, then wait for the group (the wait ends with a workgroup
+      // barrier, after which the buffers may be overwritten)
+      draw(t + 1, 0, 4, coef_next);
+      pin_noise(0, 4);
       xcd_group_arrive(bar, xcd_mode, tid);
-      draw_noise_half(t + 1, 0);
-      pin_noise_half(0);
+      draw(t + 1, 4, 2, coef_next);
+      pin_noise(4, 2);
       unsigned seen = 0;
       __builtin_amdgcn_sched_barrier(0);
-      if (tid == 0) seen = ld_dev(bar);
+      if (tid == 0) seen = ld_dev(bar);  // polled once ahead, read after the last draws
       __builtin_amdgcn_sched_barrier(0);
-      draw_noise_half(t + 1, 2);
-      pin_noise_half(2);
+      draw(t + 1, 6, 2, coef_next);
+      pin_noise(6, 2);
       aborted = xrj_group_wait(x, bar, (unsigned)++epoch, xcd_mode, tid, seen, &abort_word);
     }
   }
 
   // ---- final state and readout ---------------------------------------------------------------
+  int lane_f = lane;
+  asm volatile("" : "+v"(lane_f));
+  const int row0f = rb * XR8_ROWS + 64 * wave + 4 * (lane_f >> 4);
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int r = rgroup0 + 16 * ct + c;
+  for (int ct = 0; ct < CT; ++ct) {
+    const int r = rgroup0 + 16 * ct + (lane_f & 15);
     if (r >= a.R) continue;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = row0[rt] + v;
-        if (i < N) {
-          state[(size_t)r * N + i] = s[rt][ct][v];
-          if (a.spins) a.spins[(size_t)r * N + i] = (s[rt][ct][v] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
+        const int row = row0f + 16 * rt + v;
+        if (row < N) {
+          state[(size_t)r * N + row] = s[rt][ct][v];
+          if (a.spins) a.spins[(size_t)r * N + row] = (s[rt][ct][v] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
         }
       }
   }
@@ -1142,8 +1193,8 @@ size_t xcd_chunk_bytes() { return (size_t)XCD_RG * XCD_KC * 2; }
 // address bits) was measured to make no difference on MI355X, so the rows are packed.
 int xcd_spin_stride(int Kp) { return Kp; }
 
-int xrj_rows(int fp8_spins) { return fp8_spins ? XRJ_ROWS : XRB_ROWS; }
-int xrj_group_replicas(int fp8_spins) { return fp8_spins ? XRJ_RG : XRB_RG; }
+int xrj_rows(int fp8_spins) { return fp8_spins ? XR8_ROWS : XRB_ROWS; }
+int xrj_group_replicas(int fp8_spins) { return fp8_spins ? XR8_RG : XRB_RG; }
 int xrj_kp(int n) { return n <= 512 ? 512 : ((n + 255) / 256) * 256; }
 bool xrj_fits(int n) { return xrj_kp(n) <= 2048; }
 
@@ -1209,7 +1260,7 @@ static const void* xrj8_fn(int Kp) {
 hipError_t launch_anneal_xrj8(const AnnealArgs& a, const XcdArgs& x, int groups, hipStream_t st) {
   const void* fn = xrj8_fn(a.Kp);
   if (!fn) return hipErrorInvalidValue;
-  return launch_resident(fn, groups * x.P, 256, (size_t)XRJ_NB * XRJ8_CHB, a, x, st);
+  return launch_resident(fn, groups * x.P, 256, (size_t)XR8_NB * XR8_CHB, a, x, st);
 }
 
 static const void* xrj_fn(int Kp) {
