@@ -868,7 +868,9 @@ __global__ __launch_bounds__(256, 1) void anneal_xrj(AnnealArgs a, XcdArgs x) {
 //     u ^ ((q >> 1) & 7) of its 128-byte row, so the 16 lanes a ds_read_b128 serves hit 16
 //     distinct 16-byte bank groups. A CU receives 64 KB of spins per iteration, one buffer per
 //     chunk, loaded by direct-to-LDS buffer loads in batches of XR8_GB chunks (one workgroup
-//     barrier per batch, as in anneal_xrj).
+//     barrier per batch, as in anneal_xrj). With chunks half the size of the BF16 kernel's, one
+//     batch of every loaded chunk, issued when the iteration starts, measured fastest (25.0 ms per
+//     headline anneal, against 26.1 for batches of seven and 27.4 for batches of three).
 //   * The chunks are visited from the workgroup's own rows (two chunks), which the epilogue writes
 //     into buffers 0 and 1 as well as to memory; the fragments of the next chunk are read into a
 //     second register set while the MFMAs of the current one run.
@@ -879,7 +881,7 @@ constexpr int XR8_ROWS = 256;                  // rows of J per workgroup (64 pe
 constexpr int XR8_RG = 32;                     // replicas per group
 constexpr int XR8_KC = 128;                    // k per spin chunk
 constexpr int XR8_NB = 16;                     // spin chunk buffers in LDS (one per chunk at Kp = 2048)
-constexpr int XR8_GB = 3;                      // loaded chunks per workgroup barrier (and per batch of loads)
+constexpr int XR8_GB = 14;                     // loaded chunks per batch: all of them at Kp = 2048
 constexpr int XR8_CHB = XR8_RG * XR8_KC;       // bytes of one chunk: 32 replicas x 128 k, FP8
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
