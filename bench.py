@@ -538,12 +538,12 @@ def main() -> int:
             ws, _ = timed_anneals(ss, R, T_F, [41, 42], stream)
             sp_path = ss.info()["path"]
         with nmfa.Solver(d3.J, d3.h, precision="fp8j_bf16s", force_xcd=True) as sx:
-            wx, _ = timed_anneals(sx, R, T_F, [43], stream)
+            wx, _ = timed_anneals(sx, R, T_F, [43, 44], stream)
         msd3 = float(min(ws))
         extra["degree3_maxcut_n2000"] = {
             "R": R, "t_f": T_F, "kernel_path": sp_path, "ms_per_anneal": msd3,
             "spin_updates_per_s": N * R * T_F / (msd3 * 1e-3),
-            "dense_kernel_ms_per_anneal": wx[0], "speedup_vs_dense": wx[0] / msd3,
+            "dense_kernel_ms_per_anneal": float(min(wx)), "speedup_vs_dense": float(min(wx)) / msd3,
         }
         # Moebius ladder N = 100 (ring plus chords, J = +1): FP32 path vs the FP64 path, success at
         # the closed-form ground energy -3N/2 + 4 (N/2 even: two edges stay uncut)
