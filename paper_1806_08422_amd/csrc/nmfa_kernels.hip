@@ -998,6 +998,164 @@ __global__ __launch_bounds__(256, 1) void anneal_step_tiled(AnnealArgs a, const 
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// anneal_step_tiled_f64: one FP64 iteration as a tiled matrix product with the fused FP64
+// epilogue (the validation path for large N). Workgroup (bx, by) owns rows [128 bx, +128) x
+// replicas [64 by, +64); wave w owns rows 32 w .. +31 (two 16-row tiles) for all 64 replicas
+// (four 16-column tiles): eight v_mfma_f64_16x16x4f64 accumulators. J [Mp][Kp] and S_cur
+// [Rp][Kp] (FP64, k contiguous) stream through a 3-stage LDS ring of 32-k blocks (32 KB of J and
+// 16 KB of S per stage), filled by direct-to-LDS loads issued two blocks ahead. A block is four
+// 8-k windows of two MFMA steps; in window i, step s, lane group g carries k = 8 i + 2 g + s for
+// A and B alike (a dot product does not depend on the order of its terms), so every lane reads
+// both steps' operands with one ds_read_b128. The 16-byte unit u of tile row q is stored at
+// u ^ (q & 15) of its 256-byte row, so the 8 lanes one LDS cycle serves hit 8 distinct bank
+// groups (the A rows of a 16-row tile are permuted as the FP64 instruction's output needs, which
+// keeps them distinct modulo 16). Needs Mp % 128 == 0, Kp % 32 == 0 and S buffers of Rp rows
+// (padding rows zero).
+// ------------------------------------------------------------------------------------------
+constexpr int SF_M = 128;                     // rows per workgroup
+constexpr int SF_R = 64;                      // replicas per workgroup
+constexpr int SF_K = 32;                      // k per block
+constexpr int SF_STAGES = 3;
+constexpr int SF_JT = SF_M * SF_K * 8;        // bytes of the J tile of one block (32 KB)
+constexpr int SF_STAGE = SF_JT + SF_R * SF_K * 8;  // J tile + S tile (48 KB)
+constexpr int SF_LPW = SF_STAGE / 1024 / 4;   // 1 KB direct-to-LDS loads per wave and block (12)
+
+__global__ __launch_bounds__(256, 1) void anneal_step_tiled_f64(AnnealArgs a, const double* __restrict__ S_cur,
+                                                                double* __restrict__ S_next, int t) {
+  using Tr = Traits<PREC_FP64>;
+  extern __shared__ __align__(16) unsigned char smem_sf[];  // SF_STAGES x (J tile, S tile)
+  const int N = a.N, Kp = a.Kp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int m0 = blockIdx.x * SF_M, r0 = blockIdx.y * SF_R;
+
+  // direct-to-LDS loads: 48 blocks of 1 KB per stage (blocks 0..31 the J tile, 32..47 the S
+  // tile, four tile rows each); wave w issues blocks 12 w .. 12 w + 11. Lane l fills position
+  // l % 16 of tile row 4 (b % 32) + l / 16 with the global unit the swizzle puts there.
+  size_t goff[SF_LPW];
+#pragma unroll
+  for (int u = 0; u < SF_LPW; ++u) {
+    const int b = SF_LPW * wave + u;
+    const bool is_j = b < 32;
+    const int q = 4 * (is_j ? b : b - 32) + (lane >> 4);
+    const int unit = (lane & 15) ^ (q & 15);
+    goff[u] = is_j ? ((size_t)(m0 + q) * Kp + 2 * unit) * 8 : ((size_t)(r0 + q) * Kp + 2 * unit) * 8;
+  }
+  const unsigned char* Jb = reinterpret_cast<const unsigned char*>(a.J);
+  const unsigned char* Sb = reinterpret_cast<const unsigned char*>(S_cur);
+  unsigned char* ring = smem_sf;
+  auto issue = [&](int kb, int stage) {
+#pragma unroll
+    for (int u = 0; u < SF_LPW; ++u) {
+      const int b = SF_LPW * wave + u;
+      const unsigned char* src = (b < 32 ? Jb : Sb) + goff[u] + (size_t)kb * SF_K * 8;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(src), ring + stage * SF_STAGE + b * 1024,
+                                       16, 0, 0);
+    }
+  };
+  // fragment offsets within a stage: A row 32 wave + 16 rt + a_row(c), B replica 16 ct + c; window
+  // i reads unit 4 i + g of its row
+  int aoff[2][4], boff[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int q = 32 * wave + 16 * rt + Tr::a_row(c);
+      aoff[rt][i] = q * 256 + (((4 * i + g) ^ (q & 15)) * 16);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int q = 16 * ct + c;
+      boff[ct][i] = SF_JT + q * 256 + (((4 * i + g) ^ (q & 15)) * 16);
+    }
+  }
+
+  f64x4 acc[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0;
+
+  const int nkb = Kp / SF_K;
+  issue(0, 0);
+  if (nkb > 1) issue(1, 1);
+  for (int kb = 0; kb < nkb; ++kb) {
+    // this wave's part of block kb has landed (block kb + 1 may still be in flight)
+    if (kb + 1 < nkb) step_wait_vm<SF_LPW>();
+    else step_wait_vm<0>();
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();  // every wave's part landed; every wave is done with block kb - 1
+    __builtin_amdgcn_sched_barrier(0);
+    if (kb + 2 < nkb) issue(kb + 2, (kb + 2) % SF_STAGES);
+    const unsigned char* base = ring + (kb % SF_STAGES) * SF_STAGE;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double2 af[2], bfr[4];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) af[rt] = *reinterpret_cast<const double2*>(base + aoff[rt][i]);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) bfr[ct] = *reinterpret_cast<const double2*>(base + boff[ct][i]);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          acc[rt][ct] = Tr::mfma(af[rt].x, bfr[ct].x, acc[rt][ct]);
+          acc[rt][ct] = Tr::mfma(af[rt].y, bfr[ct].y, acc[rt][ct]);
+        }
+    }
+    // the reads of this block are complete before the next barrier frees its buffer
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // ---- fused FP64 epilogue (the one every FP64 kernel shares) ----------------------------------
+  const double* inv_g = reinterpret_cast<const double*>(a.inv_norm);
+  const double* h_g = reinterpret_cast<const double*>(a.hterm);
+  double* state = reinterpret_cast<double*>(a.state);
+  double* traj = reinterpret_cast<double*>(a.traj);
+  const double coef_t = reinterpret_cast<const double*>(a.coef)[t - 1];
+  const int k_rec = t - a.t_begin;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    const int row0 = m0 + 32 * wave + 16 * rt + 4 * g;
+    double inv[4], hv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      inv[v] = inv_g[row0 + v];
+      hv[v] = h_g[row0 + v];
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int r = r0 + 16 * ct + c;
+      const bool live_r = r < a.R;
+      double s[4], fld[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        fld[v] = acc[rt][ct][v];
+        s[v] = (live_r && row0 + v < N) ? state[(size_t)r * N + row0 + v] : 0.0;
+      }
+      Epilogue<PREC_FP64>::apply(fld, inv, hv, s, a, coef_t, (uint32_t)(row0 >> 2), (uint32_t)r, (uint32_t)t);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (row0 + v >= N || !live_r) s[v] = 0.0;
+      double* dst = S_next + (size_t)r * Kp + row0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[v] = s[v];
+      if (live_r) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (row0 + v < N) {
+            state[(size_t)r * N + row0 + v] = s[v];
+            if (traj && k_rec < a.record) traj[((size_t)k_rec * a.R + r) * N + row0 + v] = s[v];
+          }
+      }
+    }
+  }
+}
+
 hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
                               hipStream_t st) {
   if ((prec == PREC_BF16 || prec == PREC_FP8J_BF16S) && a.Mp % ST_M == 0 && a.Kp % ST_K == 0) {
@@ -1007,6 +1165,15 @@ hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, 
     if (e != hipSuccess) return e;
     const dim3 grid(a.Mp / ST_M, (a.R + ST_R - 1) / ST_R);
     hipLaunchKernelGGL(anneal_step_tiled, grid, dim3(256), lds, st, a, (const __bf16*)S_cur, (__bf16*)S_next, t);
+    return hipGetLastError();
+  }
+  if (prec == PREC_FP64 && a.Mp % SF_M == 0 && a.Kp % SF_K == 0 && a.Rp % SF_R == 0) {
+    const size_t lds = (size_t)SF_STAGES * SF_STAGE;
+    hipError_t e = hipFuncSetAttribute((const void*)anneal_step_tiled_f64,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid(a.Mp / SF_M, a.Rp / SF_R);
+    hipLaunchKernelGGL(anneal_step_tiled_f64, grid, dim3(256), lds, st, a, (const double*)S_cur, (double*)S_next, t);
     return hipGetLastError();
   }
   const dim3 grid(a.Mp / 64, a.Rp / 64);

@@ -103,9 +103,11 @@ def test_fp64_success_matches_oracle_sk20(nmfa):
 
 
 @pytest.mark.parametrize("n,R,force_step", [(1, 5, False), (17, 33, False), (70, 100, True),
-                                           (130, 70, True)])
+                                           (130, 70, True), (300, 130, True)])
 def test_fp64_ragged_shapes(nmfa, n, R, force_step):
-    """Ragged spins and replicas (not multiples of the 16/64 tiles), a single spin, fields."""
+    """Ragged spins and replicas (not multiples of the 16/64 tiles), a single spin, fields. The
+    per-iteration FP64 kernel works on 128-row x 64-replica workgroup tiles: n = 300, R = 130 spans
+    3 x 3 of them with ragged last tiles."""
     inst = instances.gnp(n, 0.5, 3) if n > 1 else instances.Instance(np.zeros((1, 1)), np.zeros(1), "one")
     h = np.round(instances.gaussian_fields(n, 2.0, 4))
     inst.h = h
