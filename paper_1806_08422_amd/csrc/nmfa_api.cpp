@@ -481,7 +481,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->jfmt = x_jfmt;
     c->nbuf = x_nbuf;
   } else {
-    c->Mp = (int)round_up(n, 128);  // the tiled per-iteration kernel works on 128-row tiles
+    c->Mp = (int)round_up(n, 256);  // the tiled per-iteration kernels work on 256-row (BF16) and 128-row (FP64) tiles
     c->Kp = c->Mp;
     c->lds_stride = 0;
   }

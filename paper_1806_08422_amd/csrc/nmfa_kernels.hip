@@ -852,19 +852,23 @@ size_t small_lds_bytes(int prec, int Mp, int stride) {
 
 // ------------------------------------------------------------------------------------------
 // anneal_step_tiled: one iteration for large N with BF16 operands (BF16 and FP8-J precisions),
-// as a tiled matrix product with the fused epilogue. Workgroup (bx, by) owns rows
-// [128 bx, +128) x replicas [128 by, +128); wave w owns rows 64 (w / 2) .. +63 and replicas
-// 64 (w % 2) .. +63 (4 x 4 MFMA tiles of 16 x 16). J [Mp][Kp] and S_cur [Rp][Kp] (both k
-// contiguous) stream through a 4-stage LDS ring of 64-k blocks filled by direct-to-LDS loads
-// (32 KB per stage: 128 rows of J and 128 replicas of S, 128 bytes each); unit u (8 k) of tile row
-// q sits at u ^ ((q >> 1) & 7) of its row, so the 16 lanes a ds_read_b128 serves hit distinct
-// bank groups. Needs Mp % 128 == 0, S buffers of roundup(R, 128) rows (padding rows zero).
+// as a tiled matrix product with the fused epilogue. Workgroup (bx, by) owns rows [256 bx, +256)
+// x replicas [128 by, +128) with eight waves (two per SIMD); wave w owns rows 64 (w / 2) .. +63
+// and replicas 64 (w % 2) .. +63 (4 x 4 MFMA tiles of 16 x 16). J [Mp][Kp] and S_cur [Rp][Kp]
+// (both k contiguous) stream through a 3-stage LDS ring of 64-k blocks (48 KB per stage: 256 rows
+// of J and 128 replicas of S, 128 bytes each) filled by direct-to-LDS loads issued two blocks
+// ahead; unit u (8 k) of tile row q sits at u ^ ((q >> 1) & 7) of its row, so the 16 lanes a
+// ds_read_b128 serves hit distinct bank groups. At N = 8192, R = 1024 this is one workgroup per
+// CU, and a quarter fewer bytes per flop come from L2 than with 128 x 128 tiles (measured 28.7
+// against 36.4 ms per 200-iteration anneal). Needs Mp % 256 == 0 and S buffers of roundup(R, 128)
+// rows (padding rows zero).
 // ------------------------------------------------------------------------------------------
-constexpr int ST_M = 128;                 // rows per workgroup
+constexpr int ST_M = 256;                 // rows per workgroup
 constexpr int ST_R = 128;                 // replicas per workgroup
 constexpr int ST_K = 64;                  // k per block
-constexpr int ST_TILE = ST_M * ST_K * 2;  // bytes of one operand tile (16 KB)
-constexpr int ST_STAGES = 4;
+constexpr int ST_JT = ST_M * ST_K * 2;    // bytes of the J tile of one block (32 KB)
+constexpr int ST_STAGE = ST_JT + ST_R * ST_K * 2;  // J tile + S tile (48 KB)
+constexpr int ST_STAGES = 3;
 
 template <int NV>
 __device__ __forceinline__ void step_wait_vm() {
@@ -872,35 +876,43 @@ __device__ __forceinline__ void step_wait_vm() {
   __builtin_amdgcn_s_waitcnt(0xF70 | (NV & 15) | ((NV >> 4) << 14));
 }
 
-__global__ __launch_bounds__(256, 1) void anneal_step_tiled(AnnealArgs a, const __bf16* __restrict__ S_cur,
-                                                            __bf16* __restrict__ S_next, int t) {
-  extern __shared__ __align__(16) unsigned char smem_st[];  // ST_STAGES x (J tile, S tile)
+// The body takes the kernel arguments by reference, which measured 2% faster than the same code in
+// the kernel itself (the compiler then reads the arguments where they are used).
+__device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf16* __restrict__ S_cur,
+                                                __bf16* __restrict__ S_next, int t) {
+  constexpr int NS = ST_STAGES, LA = NS - 1;
+  constexpr int LPW = ST_STAGE / 1024 / 8;  // 1 KB direct-to-LDS loads per wave and block (6)
+  constexpr int JB = ST_M / 8;              // 1 KB blocks of the J tile (eight 128-byte rows each)
+  extern __shared__ __align__(16) unsigned char smem_st[];  // NS x (J tile, S tile)
   const int N = a.N, Kp = a.Kp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g4 = lane >> 4, c = lane & 15;
   const int m0 = blockIdx.x * ST_M, r0 = blockIdx.y * ST_R;
   const int wm = 64 * (wave >> 1), wr = 64 * (wave & 1);
 
-  // direct-to-LDS loads: 32 blocks of 1 KB per stage, wave w issues blocks 8w .. 8w + 7 (waves 0
-  // and 1 the J tile, waves 2 and 3 the S tile); block b holds tile rows 8 (b % 16) .. +7 and lane
-  // l fills position l % 8 of row 8 (b % 16) + l / 8 with the global unit the swizzle puts there
-  const unsigned char* src = reinterpret_cast<const unsigned char*>(wave < 2 ? a.J : (const void*)S_cur);
-  const int row_base = wave < 2 ? m0 : r0;
-  size_t goff[8];
+  // direct-to-LDS loads: blocks 0 .. JB - 1 hold the J tile, JB .. JB + 15 the S tile, eight tile
+  // rows each; wave w issues blocks LPW w .. LPW w + LPW - 1. Lane l fills position l % 8 of row
+  // 8 b' + l / 8 (b' the block within its tile) with the global unit the swizzle puts there.
+  size_t goff[LPW];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int b = 8 * wave + u;
-    const int q = 8 * (b & 15) + (lane >> 3);
+  for (int u = 0; u < LPW; ++u) {
+    const int b = LPW * wave + u;
+    const bool is_j = b < JB;
+    const int q = 8 * (is_j ? b : b - JB) + (lane >> 3);
     const int unit = (lane & 7) ^ ((q >> 1) & 7);
-    goff[u] = (size_t)(row_base + q) * Kp * 2 + unit * 16;
+    goff[u] = (size_t)((is_j ? m0 : r0) + q) * Kp * 2 + unit * 16;
   }
+  const unsigned char* Jb = reinterpret_cast<const unsigned char*>(a.J);
+  const unsigned char* Sb = reinterpret_cast<const unsigned char*>(S_cur);
   unsigned char* ring = smem_st;
-  const int dst_half = wave < 2 ? 0 : ST_TILE;
   auto issue = [&](int kb, int stage) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(src + goff[u] + (size_t)kb * ST_K * 2),
-                                       ring + stage * 2 * ST_TILE + dst_half + ((8 * wave + u) & 15) * 1024, 16, 0, 0);
+    for (int u = 0; u < LPW; ++u) {
+      const int b = LPW * wave + u;
+      __builtin_amdgcn_global_load_lds(
+          reinterpret_cast<const uint32_t*>((b < JB ? Jb : Sb) + goff[u] + (size_t)kb * ST_K * 2),
+          ring + stage * ST_STAGE + b * 1024, 16, 0, 0);
+    }
   };
   // fragment offsets within a tile: lane (c, g4) reads unit 4 s + g4 of row (16 t + c) at k step s
   int foff[2];
@@ -916,20 +928,22 @@ __global__ __launch_bounds__(256, 1) void anneal_step_tiled(AnnealArgs a, const 
       for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
 
   const int nkb = Kp / ST_K;
-  issue(0, 0);
-  if (nkb > 1) issue(1, 1);
-  if (nkb > 2) issue(2, 2);
+#pragma unroll
+  for (int p = 0; p < LA; ++p)
+    if (p < nkb) issue(p, p);
   for (int kb = 0; kb < nkb; ++kb) {
-    // this wave's part of block kb has landed (blocks kb + 1, kb + 2 may still be in flight)
-    if (kb + 2 < nkb) step_wait_vm<16>();
-    else if (kb + 1 < nkb) step_wait_vm<8>();
-    else step_wait_vm<0>();
+    // this wave's part of block kb has landed (the blocks after it may still be in flight)
+    const int rem = nkb - 1 - kb;
+    if (rem >= LA - 1) step_wait_vm<LPW * (LA - 1)>();
+    else if (rem == 0) step_wait_vm<0>();
+    else if (rem == 1) step_wait_vm<LPW>();
+    else step_wait_vm<2 * LPW>();
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_barrier();  // every wave's part landed; every wave is done with block kb - 1
     __builtin_amdgcn_sched_barrier(0);
-    if (kb + 3 < nkb) issue(kb + 3, (kb + 3) % ST_STAGES);
-    const unsigned char* At = ring + (kb % ST_STAGES) * 2 * ST_TILE + wm * 128;
-    const unsigned char* Bt = ring + (kb % ST_STAGES) * 2 * ST_TILE + ST_TILE + wr * 128;
+    if (kb + LA < nkb) issue(kb + LA, (kb + LA) % NS);
+    const unsigned char* At = ring + (kb % NS) * ST_STAGE + wm * 128;
+    const unsigned char* Bt = ring + (kb % NS) * ST_STAGE + ST_JT + wr * 128;
     // both k steps' fragments are read up front, so the second step's reads land under the
     // first step's MFMAs
     bf16x8 af[2][4], bfr[2][4];
@@ -996,6 +1010,11 @@ __global__ __launch_bounds__(256, 1) void anneal_step_tiled(AnnealArgs a, const 
       }
     }
   }
+}
+
+__global__ __launch_bounds__(512, 1) void anneal_step_tiled(AnnealArgs a, const __bf16* __restrict__ S_cur,
+                                                            __bf16* __restrict__ S_next, int t) {
+  step_tiled_body(a, S_cur, S_next, t);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1159,12 +1178,12 @@ __global__ __launch_bounds__(256, 1) void anneal_step_tiled_f64(AnnealArgs a, co
 hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
                               hipStream_t st) {
   if ((prec == PREC_BF16 || prec == PREC_FP8J_BF16S) && a.Mp % ST_M == 0 && a.Kp % ST_K == 0) {
-    const size_t lds = (size_t)ST_STAGES * 2 * ST_TILE;
+    const size_t lds = (size_t)ST_STAGES * ST_STAGE;
     hipError_t e = hipFuncSetAttribute((const void*)anneal_step_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
     const dim3 grid(a.Mp / ST_M, (a.R + ST_R - 1) / ST_R);
-    hipLaunchKernelGGL(anneal_step_tiled, grid, dim3(256), lds, st, a, (const __bf16*)S_cur, (__bf16*)S_next, t);
+    hipLaunchKernelGGL(anneal_step_tiled, grid, dim3(512), lds, st, a, (const __bf16*)S_cur, (__bf16*)S_next, t);
     return hipGetLastError();
   }
   if (prec == PREC_FP64 && a.Mp % SF_M == 0 && a.Kp % SF_K == 0 && a.Rp % SF_R == 0) {
