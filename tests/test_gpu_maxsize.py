@@ -1,11 +1,11 @@
 """Parity at large sizes, up to the largest instance the library accepts, n = 16384.
 
 Above n = 2048 a dense instance runs on the per-iteration kernels (the tiled BF16 matrix product
-for the BF16-operand precisions, the direct one for FP32 / FP64) and a degree-3 graph on the
-generic sparse kernel (the register-ELL variant stops at n = 4096). All are checked against the
-FP64 oracle: FP32 trajectories of every replica for the first iterations to 1e-4, BF16 ones to
-5e-3 (BF16 operand rounding of states of order 0.1), and the exact integer energies of the readout
-bit for bit.
+for the BF16-operand precisions, the tiled FP64 one for FP64, the direct one for FP32) and a
+degree-3 graph on the generic sparse kernel (the register-ELL variant stops at n = 4096). All are
+checked against the FP64 oracle: FP64 trajectories of every replica for the first iterations to
+1e-9, FP32 ones to 1e-4, BF16 ones to 5e-3 (BF16 operand rounding of states of order 0.1), and the
+exact integer energies of the readout bit for bit.
 """
 import numpy as np
 import pytest
@@ -52,8 +52,20 @@ def test_bf16_tiled_step_at_max_n(nmfa):
     _check(nmfa, instances.sk(N, 6), R=3, t_f=8, seed=5, expect_path="step", precision="bf16", tol=5e-3)
 
 
+def test_fp64_tiled_step_at_max_n(nmfa):
+    _check(nmfa, instances.sk(N, 8), R=3, t_f=8, seed=6, expect_path="step", precision="fp64", tol=1e-9)
+
+
+def test_fp64_tiled_step_ragged(nmfa):
+    # n = 4100 (33 row tiles of 128, the last nearly empty), R = 70 (two replica tiles of 64, the
+    # second ragged), with fields
+    inst = instances.sk(4100, 11)
+    inst.h = np.round(instances.gaussian_fields(4100, 1.0, 5))
+    _check(nmfa, inst, R=70, t_f=8, seed=12, expect_path="step", precision="fp64", tol=1e-9)
+
+
 def test_bf16_tiled_step_ragged(nmfa):
-    # n = 4100 (33 row tiles of 128, the last nearly empty), R = 200 (two replica tiles, the second
+    # n = 4100 (17 row tiles of 256, the last nearly empty), R = 200 (two replica tiles, the second
     # ragged), with fields; then replica-prefix and resume invariance, bit for bit
     inst = instances.sk(4100, 7)
     inst.h = np.round(instances.gaussian_fields(4100, 1.0, 3))
