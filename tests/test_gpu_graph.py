@@ -6,7 +6,7 @@ eager anneals of other seeds in between, checking every replay's energies and sp
 first eager run. The cases cover every kernel path: the persistent small-N kernel (BF16 and
 FP64), the group kernels (register-J with BF16 and with FP8 spins, LDS-J; a zero-fill kernel
 clears their control block inside the run), the sparse kernels (register and generic), and the
-per-iteration kernels (tiled BF16 and plain FP32). A last test checks that a replayed group-kernel
+per-iteration kernels (tiled BF16, tiled FP64 and plain FP32). A last test checks that a replayed group-kernel
 run whose abort word is set is reported when its results are read.
 """
 import numpy as np
@@ -94,6 +94,12 @@ def test_graph_replay_generic_sparse_kernel(env):
     nmfa, torch = env
     path = _replays_match(nmfa, torch, instances.random_regular(1000, 4, 48), 96, 120, 84, sparse_generic=True)
     assert path == "sparse"
+
+
+def test_graph_replay_fp64_tiled_step_kernel(env):
+    nmfa, torch = env
+    path = _replays_match(nmfa, torch, instances.sk(300, 51), 100, 40, 86, precision="fp64", force_step=True)
+    assert path == "step"
 
 
 def test_graph_replay_fp32_step_kernel(env):
