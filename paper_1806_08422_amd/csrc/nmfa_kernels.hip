@@ -13,9 +13,14 @@
 //   anneal_small<P>   persistent: one workgroup owns 16 replicas and all N <= 256 spins for the
 //                     whole anneal. J sits in LDS, the operand copy of S is double-buffered in
 //                     LDS, the master state lives in registers; one barrier per iteration.
-//   anneal_step<P>    one iteration for large N: each wave owns 16 rows x 64 replicas, reads
-//                     J and S straight from global memory (L2), updates the master state in
-//                     HBM and writes the next operand copy of S.
+//   anneal_step<P>    one iteration for large N (FP32; FP64 only for shapes the tiled FP64
+//                     kernel does not take): each wave owns 16 rows x 64 replicas, reads J and S
+//                     straight from global memory (L2), updates the master state in HBM and
+//                     writes the next operand copy of S.
+//   anneal_step_tiled, anneal_step_tiled_f64
+//                     the same iteration as tiled matrix products through LDS (BF16 operands on
+//                     256 x 128 workgroup tiles, FP64 on 128 x 64), with the fused epilogue.
+//   anneal_sparse*    degree-d graphs with J in ELL rows (see their own comments).
 //   readout_kernel    s~ = sign(s) (s = 0 reads +1).
 //   energy_kernel     exact integer energies for integral J (int8) and integral h, or an
 //                     integral pair term plus an FP64 field term summed in ascending i; with
