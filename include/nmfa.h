@@ -205,10 +205,11 @@ int nmfa_trajectory(nmfa_ctx *c, double *out);
 int nmfa_info(nmfa_ctx *c, int32_t *n, int32_t *precision, int32_t *path);
 
 /* Storage format of J in device memory as the annealing kernel reads it. For the BF16-operand
- * precisions J (already rounded as the precision prescribes, Sec. III) is kept in the narrowest
- * of these formats that holds every coupling exactly and is widened to BF16 in registers:
- * NMFA_JFMT_BF16, NMFA_JFMT_FP8 (E4M3), NMFA_JFMT_FP4 (E2M1). NMFA_JFMT_NATIVE: J in the
- * precision's own type (FP64, FP32). Errors: EINVAL. */
+ * precisions on the group and per-iteration kernels J (already rounded as the precision
+ * prescribes, Sec. III) is kept in the narrowest of these formats that holds every coupling
+ * exactly and is widened to BF16 in registers: NMFA_JFMT_BF16, NMFA_JFMT_FP8 (E4M3),
+ * NMFA_JFMT_FP4 (E2M1); the small-N kernel keeps BF16 (FP8 for NMFA_FP8J_BF16S).
+ * NMFA_JFMT_NATIVE: J in the precision's own type (FP64, FP32). Errors: EINVAL. */
 #define NMFA_JFMT_BF16 0
 #define NMFA_JFMT_FP8 1
 #define NMFA_JFMT_FP4 2

@@ -484,6 +484,7 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
     c->Mp = (int)round_up(n, 256);  // the tiled per-iteration kernels work on 256-row (BF16) and 128-row (FP64) tiles
     c->Kp = c->Mp;
     c->lds_stride = 0;
+    c->jfmt = bf ? x_jfmt : 0;  // BF16-operand precisions: J streamed as FP4 / FP8 where exact
   }
   c->Ks = c->path == 2 ? xcd_spin_stride(c->Kp) : c->Kp;
   const int Mp = c->Mp, Kp = c->Kp;
@@ -498,9 +499,10 @@ extern "C" int nmfa_create(int32_t n, const double* J, const double* h, const nm
   }
 
   // operand copy of J: FP8 bytes for the small FP8-J kernel; FP4 / FP8 / BF16 for the XCD-group
-  // kernel; else the precision's operand type (FP8-J on the per-iteration path: FP8-rounded BF16)
+  // kernel and the tiled per-iteration kernel of the BF16-operand precisions; else the precision's
+  // operand type
   const bool j8_small = (c->prec == NMFA_FP8J_BF16S && c->path == 0);
-  const int jfmt2 = (c->path == 2) ? c->jfmt : -1;
+  const int jfmt2 = (c->path == 2 || (c->path == 1 && bf)) ? c->jfmt : -1;
   size_t jbytes;
   if (c->path == 3) jbytes = 0;  // the sparse kernel reads its ELL copy instead
   else if (j8_small || jfmt2 == 1) jbytes = (size_t)Mp * Kp;
@@ -847,7 +849,7 @@ int ctx_launch_run(nmfa_ctx* c, int32_t R, int32_t t_f, int32_t t_begin, int32_t
     HIP_TRY(hipEventRecord(c->ev0, st));
     int cur = 0;
     for (int t = t_begin; t <= t_end; ++t) {
-      HIP_TRY(launch_anneal_step(c->prec, a, c->d_S[cur], c->d_S[cur ^ 1], t, st));
+      HIP_TRY(launch_anneal_step(c->prec, c->path == 1 ? c->jfmt : 0, a, c->d_S[cur], c->d_S[cur ^ 1], t, st));
       cur ^= 1;
     }
     c->launches = t_end - t_begin + 1;
@@ -1064,6 +1066,7 @@ extern "C" int nmfa_info(nmfa_ctx* c, int32_t* n, int32_t* precision, int32_t* p
 extern "C" int nmfa_j_format(nmfa_ctx* c, int32_t* fmt) {
   if (!c || !fmt) return fail(NMFA_EINVAL, "nmfa_j_format: NULL argument");
   if (c->path == 2) *fmt = c->jfmt;
+  else if (c->path == 1 && c->prec != NMFA_FP64 && c->prec != NMFA_FP32) *fmt = c->jfmt;
   else if (c->path == 3) *fmt = NMFA_JFMT_ELL;
   else if (c->prec == NMFA_FP64 || c->prec == NMFA_FP32) *fmt = NMFA_JFMT_NATIVE;
   else if (c->prec == NMFA_FP8J_BF16S && c->path == 0) *fmt = NMFA_JFMT_FP8;

@@ -62,7 +62,9 @@ hipError_t launch_zero_words(uint32_t* p, size_t a0, size_t a1, size_t b0, size_
 int xcd_rows();
 int xcd_group_replicas();
 size_t small_lds_bytes(int prec, int Mp, int stride);
-hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
+// jfmt: storage format of J for the BF16-operand precisions (0 = BF16, 1 = FP8 E4M3, 2 = FP4 E2M1;
+// the tiled kernel widens FP8 / FP4 to BF16); 0 for FP32 / FP64
+hipError_t launch_anneal_step(int prec, int jfmt, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
                               hipStream_t st);
 // Writes rows [0, Rp) x columns [0, Kp) of S (row stride ld) from the master state (zero: all 0).
 hipError_t launch_pack_state(int prec, const void* state, void* S, int N, int R, int Kp, int ld, int Rp, int zero,

@@ -867,13 +867,51 @@ size_t small_lds_bytes(int prec, int Mp, int stride) {
 // CU, and a quarter fewer bytes per flop come from L2 than with 128 x 128 tiles (measured 28.7
 // against 36.4 ms per 200-iteration anneal). Needs Mp % 256 == 0 and S buffers of roundup(R, 128)
 // rows (padding rows zero).
+// JFMT: format of J in memory and LDS, the narrowest that holds the couplings exactly (0 = BF16,
+// 1 = FP8 E4M3, 2 = FP4 E2M1), widened to BF16 in registers: the kernel is bound by streaming its
+// tiles from L2, and FP8 / FP4 rows of 64 / 32 bytes per block cut the J bytes to a half / a
+// quarter. Unit u (16 bytes) of J row q sits at u ^ f(q) with f = (q >> 1) & 7, (q >> 2) & 3,
+// (q >> 3) & 1 for the three formats, so the 16 rows one fragment read spans hit distinct banks.
 // ------------------------------------------------------------------------------------------
 constexpr int ST_M = 256;                 // rows per workgroup
 constexpr int ST_R = 128;                 // replicas per workgroup
 constexpr int ST_K = 64;                  // k per block
-constexpr int ST_JT = ST_M * ST_K * 2;    // bytes of the J tile of one block (32 KB)
-constexpr int ST_STAGE = ST_JT + ST_R * ST_K * 2;  // J tile + S tile (48 KB)
 constexpr int ST_STAGES = 3;
+
+template <int JFMT>
+struct StFmt {
+  static constexpr int JRB = JFMT == 0 ? 128 : (JFMT == 1 ? 64 : 32);  // bytes of a J row per block
+  static constexpr int JT = ST_M * JRB;                               // bytes of the J tile
+  static constexpr int STAGE = JT + ST_R * ST_K * 2;                  // J tile + S tile (128-byte rows)
+  static constexpr int JB = JT / 1024;                                // 1 KB blocks of the J tile
+  static constexpr int LPW = STAGE / 1024 / 8;                        // 1 KB loads per wave and block
+  static constexpr int UPR = JRB / 16;                                // 16-byte units per J row
+  __device__ static __forceinline__ int swz(int q) {
+    return JFMT == 0 ? ((q >> 1) & 7) : (JFMT == 1 ? ((q >> 2) & 3) : ((q >> 3) & 1));
+  }
+};
+static_assert(StFmt<0>::LPW * 8 * 1024 == StFmt<0>::STAGE && StFmt<1>::LPW * 8 * 1024 == StFmt<1>::STAGE &&
+                  StFmt<2>::LPW * 8 * 1024 == StFmt<2>::STAGE,
+              "every wave issues the same number of 1 KB loads per block");
+
+// 8 FP8 E4M3 (two words) or 8 FP4 E2M1 values (one word; value 2b in the low nibble of byte b)
+// widened to BF16 (exact for every value of either format)
+__device__ __forceinline__ bf16x8 tiled_widen_fp8(uint2 v) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.x, 1.0f, false);
+  const bf16x2 p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.x, 1.0f, true);
+  const bf16x2 p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.y, 1.0f, false);
+  const bf16x2 p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.y, 1.0f, true);
+  return bf16x8{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+}
+__device__ __forceinline__ bf16x8 tiled_widen_fp4(uint32_t w) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 0);
+  const bf16x2 p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 1);
+  const bf16x2 p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 2);
+  const bf16x2 p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp4(w, 1.0f, 3);
+  return bf16x8{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+}
 
 template <int NV>
 __device__ __forceinline__ void step_wait_vm() {
@@ -883,11 +921,12 @@ __device__ __forceinline__ void step_wait_vm() {
 
 // The body takes the kernel arguments by reference, which measured 2% faster than the same code in
 // the kernel itself (the compiler then reads the arguments where they are used).
+template <int JFMT>
 __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf16* __restrict__ S_cur,
                                                 __bf16* __restrict__ S_next, int t) {
+  using F = StFmt<JFMT>;
   constexpr int NS = ST_STAGES, LA = NS - 1;
-  constexpr int LPW = ST_STAGE / 1024 / 8;  // 1 KB direct-to-LDS loads per wave and block (6)
-  constexpr int JB = ST_M / 8;              // 1 KB blocks of the J tile (eight 128-byte rows each)
+  constexpr int LPW = F::LPW, JB = F::JB, JRB = F::JRB, UPR = F::UPR;
   extern __shared__ __align__(16) unsigned char smem_st[];  // NS x (J tile, S tile)
   const int N = a.N, Kp = a.Kp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -895,17 +934,24 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
   const int m0 = blockIdx.x * ST_M, r0 = blockIdx.y * ST_R;
   const int wm = 64 * (wave >> 1), wr = 64 * (wave & 1);
 
-  // direct-to-LDS loads: blocks 0 .. JB - 1 hold the J tile, JB .. JB + 15 the S tile, eight tile
-  // rows each; wave w issues blocks LPW w .. LPW w + LPW - 1. Lane l fills position l % 8 of row
-  // 8 b' + l / 8 (b' the block within its tile) with the global unit the swizzle puts there.
+  // direct-to-LDS loads: blocks 0 .. JB - 1 hold the J tile (1024 / JRB rows each), JB .. JB + 15
+  // the S tile (eight 128-byte rows each); wave w issues blocks LPW w .. LPW w + LPW - 1. Lane l
+  // fills position l % (units per row) of row (rows per block) b' + l / (units per row) (b' the
+  // block within its tile) with the global unit the swizzle puts there.
+  const size_t jrow = (size_t)Kp * JRB / ST_K;  // bytes of one J row in memory
   size_t goff[LPW];
 #pragma unroll
   for (int u = 0; u < LPW; ++u) {
     const int b = LPW * wave + u;
-    const bool is_j = b < JB;
-    const int q = 8 * (is_j ? b : b - JB) + (lane >> 3);
-    const int unit = (lane & 7) ^ ((q >> 1) & 7);
-    goff[u] = (size_t)((is_j ? m0 : r0) + q) * Kp * 2 + unit * 16;
+    if (b < JB) {
+      const int q = (1024 / JRB) * b + lane / UPR;
+      const int unit = (lane % UPR) ^ F::swz(q);
+      goff[u] = (size_t)(m0 + q) * jrow + unit * 16;
+    } else {
+      const int q = 8 * (b - JB) + (lane >> 3);
+      const int unit = (lane & 7) ^ ((q >> 1) & 7);
+      goff[u] = (size_t)(r0 + q) * Kp * 2 + unit * 16;
+    }
   }
   const unsigned char* Jb = reinterpret_cast<const unsigned char*>(a.J);
   const unsigned char* Sb = reinterpret_cast<const unsigned char*>(S_cur);
@@ -915,14 +961,22 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
     for (int u = 0; u < LPW; ++u) {
       const int b = LPW * wave + u;
       __builtin_amdgcn_global_load_lds(
-          reinterpret_cast<const uint32_t*>((b < JB ? Jb : Sb) + goff[u] + (size_t)kb * ST_K * 2),
-          ring + stage * ST_STAGE + b * 1024, 16, 0, 0);
+          reinterpret_cast<const uint32_t*>((b < JB ? Jb + (size_t)kb * JRB : Sb + (size_t)kb * ST_K * 2) + goff[u]),
+          ring + stage * F::STAGE + b * 1024, 16, 0, 0);
     }
   };
-  // fragment offsets within a tile: lane (c, g4) reads unit 4 s + g4 of row (16 t + c) at k step s
-  int foff[2];
+  // fragment offsets within a 16-row tile: lane (c, g4) reads k octet o = 4 s + g4 of row c at k
+  // step s (the swizzle of row q depends on q mod 16 only): S and BF16 J in unit o, FP8 J in half
+  // o % 2 of unit o / 2, FP4 J in quarter o % 4 of unit o / 4
+  int foff[2], joff[2];
 #pragma unroll
-  for (int s = 0; s < 2; ++s) foff[s] = c * 128 + (((4 * s + g4) ^ ((c >> 1) & 7)) * 16);
+  for (int s = 0; s < 2; ++s) {
+    const int o = 4 * s + g4;
+    foff[s] = c * 128 + ((o ^ ((c >> 1) & 7)) * 16);
+    if (JFMT == 0) joff[s] = foff[s];
+    else if (JFMT == 1) joff[s] = c * 64 + (((o >> 1) ^ F::swz(c)) * 16) + (o & 1) * 8;
+    else joff[s] = c * 32 + (((o >> 2) ^ F::swz(c)) * 16) + (o & 3) * 4;
+  }
 
   f32x4 acc[4][4];
 #pragma unroll
@@ -947,8 +1001,8 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
     __builtin_amdgcn_s_barrier();  // every wave's part landed; every wave is done with block kb - 1
     __builtin_amdgcn_sched_barrier(0);
     if (kb + LA < nkb) issue(kb + LA, (kb + LA) % NS);
-    const unsigned char* At = ring + (kb % NS) * ST_STAGE + wm * 128;
-    const unsigned char* Bt = ring + (kb % NS) * ST_STAGE + ST_JT + wr * 128;
+    const unsigned char* At = ring + (kb % NS) * F::STAGE + wm * JRB;
+    const unsigned char* Bt = ring + (kb % NS) * F::STAGE + F::JT + wr * 128;
     // both k steps' fragments are read up front, so the second step's reads land under the
     // first step's MFMAs
     bf16x8 af[2][4], bfr[2][4];
@@ -956,7 +1010,10 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        af[s][i] = *reinterpret_cast<const bf16x8*>(At + 2048 * i + foff[s]);
+        const unsigned char* ap = At + 16 * JRB * i + joff[s];
+        if constexpr (JFMT == 0) af[s][i] = *reinterpret_cast<const bf16x8*>(ap);
+        else if constexpr (JFMT == 1) af[s][i] = tiled_widen_fp8(*reinterpret_cast<const uint2*>(ap));
+        else af[s][i] = tiled_widen_fp4(*reinterpret_cast<const uint32_t*>(ap));
         bfr[s][i] = *reinterpret_cast<const bf16x8*>(Bt + 2048 * i + foff[s]);
       }
 #pragma unroll
@@ -1017,9 +1074,10 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
   }
 }
 
+template <int JFMT>
 __global__ __launch_bounds__(512, 1) void anneal_step_tiled(AnnealArgs a, const __bf16* __restrict__ S_cur,
                                                             __bf16* __restrict__ S_next, int t) {
-  step_tiled_body(a, S_cur, S_next, t);
+  step_tiled_body<JFMT>(a, S_cur, S_next, t);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1180,16 +1238,26 @@ __global__ __launch_bounds__(256, 1) void anneal_step_tiled_f64(AnnealArgs a, co
   }
 }
 
-hipError_t launch_anneal_step(int prec, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
+template <int JFMT>
+static hipError_t launch_step_tiled(const AnnealArgs& a, const void* S_cur, void* S_next, int t, hipStream_t st) {
+  const size_t lds = (size_t)ST_STAGES * StFmt<JFMT>::STAGE;
+  hipError_t e = hipFuncSetAttribute((const void*)anneal_step_tiled<JFMT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid(a.Mp / ST_M, (a.R + ST_R - 1) / ST_R);
+  hipLaunchKernelGGL(anneal_step_tiled<JFMT>, grid, dim3(512), lds, st, a, (const __bf16*)S_cur, (__bf16*)S_next, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_anneal_step(int prec, int jfmt, const AnnealArgs& a, const void* S_cur, void* S_next, int t,
                               hipStream_t st) {
-  if ((prec == PREC_BF16 || prec == PREC_FP8J_BF16S) && a.Mp % ST_M == 0 && a.Kp % ST_K == 0) {
-    const size_t lds = (size_t)ST_STAGES * ST_STAGE;
-    hipError_t e = hipFuncSetAttribute((const void*)anneal_step_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    const dim3 grid(a.Mp / ST_M, (a.R + ST_R - 1) / ST_R);
-    hipLaunchKernelGGL(anneal_step_tiled, grid, dim3(512), lds, st, a, (const __bf16*)S_cur, (__bf16*)S_next, t);
-    return hipGetLastError();
+  if (prec == PREC_BF16 || prec == PREC_FP8J_BF16S) {
+    if (a.Mp % ST_M == 0 && a.Kp % ST_K == 0) {
+      if (jfmt == 2) return launch_step_tiled<2>(a, S_cur, S_next, t, st);
+      if (jfmt == 1) return launch_step_tiled<1>(a, S_cur, S_next, t, st);
+      return launch_step_tiled<0>(a, S_cur, S_next, t, st);
+    }
+    if (jfmt != 0) return hipErrorInvalidValue;  // the direct kernel below reads BF16 J
   }
   if (prec == PREC_FP64 && a.Mp % SF_M == 0 && a.Kp % SF_K == 0 && a.Rp % SF_R == 0) {
     const size_t lds = (size_t)SF_STAGES * SF_STAGE;

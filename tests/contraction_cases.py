@@ -126,12 +126,18 @@ CASES: List[Case] = [
     Case("small_bf16_sk100", lambda: instances.sk(100, 2), "bf16", 200, _SMALL_SUB, ("persistent",), {}),
     Case("small_fp8j_g100", lambda: instances.gnp(100, 0.5, 2), "fp8j_bf16s", 200, _SMALL_SUB, ("persistent",), {}),
     Case("small_fp32_sk100", lambda: instances.sk(100, 2), "fp32", 200, _SMALL_SUB, ("persistent",), {}),
-    # the tiled per-iteration kernel: ragged rows (300 = 2 x 128 + 44) and two replica tiles
+    # the tiled per-iteration kernel in each of its three J formats: ragged rows (300 of a 256-row
+    # tile pair) and two replica tiles
     Case("tiled_bf16_sk300", lambda: instances.sk(300, 4), "bf16", 200, _TILE_SUB, ("step",),
-         {"force_step": True}),
+         {"force_step": True}, j_format="fp4_e2m1"),
     Case("tiled_fp8j_g300", lambda: instances.gnp(300, 0.5, 4), "fp8j_bf16s", 200, _TILE_SUB, ("step",),
-         {"force_step": True}),
-    Case("tiled_fp8j_sk4100", lambda: instances.sk(4100, 7), "fp8j_bf16s", 200, _TILE_SUB, ("step",), {}),
+         {"force_step": True}, j_format="fp4_e2m1"),
+    Case("tiled_fp8_5sk300", lambda: _scaled_sk(300, 11, 5.0), "bf16", 200, _TILE_SUB, ("step",),
+         {"force_step": True}, j_format="fp8_e4m3"),
+    Case("tiled_bf16_grid300", lambda: _grid_j(300, 12), "bf16", 200, _TILE_SUB, ("step",),
+         {"force_step": True}, j_format="bf16", field=1.0 / 128),
+    Case("tiled_fp8j_sk4100", lambda: instances.sk(4100, 7), "fp8j_bf16s", 200, _TILE_SUB, ("step",), {},
+         j_format="fp4_e2m1"),
     Case("step_fp32_sk300", lambda: instances.sk(300, 4), "fp32", 200, _TILE_SUB, ("step",), {"force_step": True}),
     # the sparse kernels on a degree-3 graph
     Case("sparse_rq_d3_2000", lambda: instances.random_regular(2000, 3, 5), "bf16", 256, (0, 3, 100, 255),
