@@ -913,6 +913,11 @@ __device__ __forceinline__ bf16x8 tiled_widen_fp4(uint32_t w) {
   return bf16x8{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
 }
 
+template <bool B>
+struct StBool {
+  static constexpr bool value = B;
+};
+
 template <int NV>
 __device__ __forceinline__ void step_wait_vm() {
   static_assert(NV >= 0 && NV <= 63, "vmcnt range");
@@ -987,6 +992,39 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
       for (int v = 0; v < 4; ++v) acc[rt][ct][v] = 0.0f;
 
   const int nkb = Kp / ST_K;
+  // This wave's 64 x 64 master states are loaded before the k loop, so that their latency hides
+  // under the matrix work rather than stalling the epilogue. They are issued ahead of the first
+  // blocks, so the first block's wait also covers them. When the wave's tile lies inside N x R and
+  // N % 4 == 0 (a wave-uniform test), a lane's four rows are one 16-byte load and store.
+  float* state = reinterpret_cast<float*>(a.state);
+  const bool full = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(state) & 15) == 0 && m0 + wm + 64 <= N &&
+                    r0 + wr + 64 <= a.R;
+  float st[4][4][4];
+  if (full) {
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const float4 v4 = *reinterpret_cast<const float4*>(state + (size_t)(r0 + wr + 16 * ct + c) * N + m0 + wm +
+                                                           16 * rt + 4 * g4);
+        st[rt][ct][0] = v4.x;
+        st[rt][ct][1] = v4.y;
+        st[rt][ct][2] = v4.z;
+        st[rt][ct][3] = v4.w;
+      }
+  } else {
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int row0 = m0 + wm + 16 * rt + 4 * g4;
+        const int r = r0 + wr + 16 * ct + c;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          st[rt][ct][v] = (r < a.R && row0 + v < N) ? state[(size_t)r * N + row0 + v] : 0.0f;
+      }
+  }
+
 #pragma unroll
   for (int p = 0; p < LA; ++p)
     if (p < nkb) issue(p, p);
@@ -1031,47 +1069,62 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
   // ---- fused epilogue (the FP32 epilogue shared by every kernel) --------------------------------
   const float* inv_g = reinterpret_cast<const float*>(a.inv_norm);
   const float* h_g = reinterpret_cast<const float*>(a.hterm);
-  float* state = reinterpret_cast<float*>(a.state);
   float* traj = reinterpret_cast<float*>(a.traj);
+  if (!(traj && t - a.t_begin < a.record)) traj = nullptr;
+  else traj += (size_t)(t - a.t_begin) * a.R * N;
+  const bool vec_traj = full && (reinterpret_cast<uintptr_t>(traj) & 15) == 0;
   const float coef_t = reinterpret_cast<const float*>(a.coef)[t - 1];
-  const int k_rec = t - a.t_begin;
+  // two copies of the epilogue, so that the bounds tests of a partial tile stay out of the full one
+  auto epilogue = [&](auto full_c) {
+    constexpr bool FULL = decltype(full_c)::value;
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt) {
-    const int row0 = m0 + wm + 16 * rt + 4 * g4;
-    float inv[4], hv[4];
+    for (int rt = 0; rt < 4; ++rt) {
+      const int row0 = m0 + wm + 16 * rt + 4 * g4;
+      // inv_norm and hterm hold Mp entries (zero past N) and row0 is a multiple of 4
+      const float4 inv4 = *reinterpret_cast<const float4*>(inv_g + row0);
+      const float4 h4 = *reinterpret_cast<const float4*>(h_g + row0);
+      const float inv[4] = {inv4.x, inv4.y, inv4.z, inv4.w};
+      const float hv[4] = {h4.x, h4.y, h4.z, h4.w};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      inv[v] = inv_g[row0 + v];
-      hv[v] = h_g[row0 + v];
-    }
+      for (int ct = 0; ct < 4; ++ct) {
+        const int r = r0 + wr + 16 * ct + c;
+        const bool live_r = FULL || r < a.R;
+        float* sv = st[rt][ct];
+        float fld[4];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const int r = r0 + wr + 16 * ct + c;
-      const bool live_r = r < a.R;
-      float sv[4], fld[4];
+        for (int v = 0; v < 4; ++v) fld[v] = acc[rt][ct][v];
+        Epilogue<PREC_BF16>::apply(fld, inv, hv, sv, a, coef_t, (uint32_t)(row0 >> 2), (uint32_t)r, (uint32_t)t);
+        __bf16 outv[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        fld[v] = acc[rt][ct][v];
-        sv[v] = (live_r && row0 + v < N) ? state[(size_t)r * N + row0 + v] : 0.0f;
-      }
-      Epilogue<PREC_BF16>::apply(fld, inv, hv, sv, a, coef_t, (uint32_t)(row0 >> 2), (uint32_t)r, (uint32_t)t);
-      __bf16 outv[4];
+        for (int v = 0; v < 4; ++v) {
+          if (!FULL && (row0 + v >= N || !live_r)) sv[v] = 0.0f;
+          outv[v] = (__bf16)sv[v];
+        }
+        *reinterpret_cast<uint2*>(S_next + (size_t)r * Kp + row0) = *reinterpret_cast<const uint2*>(outv);
+        float* sp = state + (size_t)r * N + row0;
+        float* tp = traj + (size_t)r * N + row0;
+        if constexpr (FULL) {
+          const float4 o4 = make_float4(sv[0], sv[1], sv[2], sv[3]);
+          *reinterpret_cast<float4*>(sp) = o4;
+          if (traj) {
+            if (vec_traj) *reinterpret_cast<float4*>(tp) = o4;
+            else
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (row0 + v >= N || !live_r) sv[v] = 0.0f;
-        outv[v] = (__bf16)sv[v];
-      }
-      *reinterpret_cast<uint2*>(S_next + (size_t)r * Kp + row0) = *reinterpret_cast<const uint2*>(outv);
-      if (live_r) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (row0 + v < N) {
-            state[(size_t)r * N + row0 + v] = sv[v];
-            if (traj && k_rec < a.record) traj[((size_t)k_rec * a.R + r) * N + row0 + v] = sv[v];
+              for (int v = 0; v < 4; ++v) tp[v] = sv[v];
           }
+        } else if (live_r) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (row0 + v < N) {
+              sp[v] = sv[v];
+              if (traj) tp[v] = sv[v];
+            }
+        }
       }
     }
-  }
+  };
+  if (full) epilogue(StBool<true>{});
+  else epilogue(StBool<false>{});
 }
 
 template <int JFMT>
