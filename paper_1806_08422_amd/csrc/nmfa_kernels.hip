@@ -860,18 +860,20 @@ size_t small_lds_bytes(int prec, int Mp, int stride) {
 // as a tiled matrix product with the fused epilogue. Workgroup (bx, by) owns rows [256 bx, +256)
 // x replicas [128 by, +128) with eight waves (two per SIMD); wave w owns rows 64 (w / 2) .. +63
 // and replicas 64 (w % 2) .. +63 (4 x 4 MFMA tiles of 16 x 16). J [Mp][Kp] and S_cur [Rp][Kp]
-// (both k contiguous) stream through a 3-stage LDS ring of 64-k blocks (48 KB per stage: 256 rows
-// of J and 128 replicas of S, 128 bytes each) filled by direct-to-LDS loads issued two blocks
-// ahead; unit u (8 k) of tile row q sits at u ^ ((q >> 1) & 7) of its row, so the 16 lanes a
-// ds_read_b128 serves hit distinct bank groups. At N = 8192, R = 1024 this is one workgroup per
-// CU, and a quarter fewer bytes per flop come from L2 than with 128 x 128 tiles (measured 28.7
-// against 36.4 ms per 200-iteration anneal). Needs Mp % 256 == 0 and S buffers of roundup(R, 128)
-// rows (padding rows zero).
+// (both k contiguous) stream through a 3-stage LDS ring of 64-k blocks (256 rows of J and 128
+// replicas of S per stage) filled by direct-to-LDS loads issued two blocks ahead; unit u (8 k) of
+// S row q sits at u ^ ((q >> 1) & 7) of its 128-byte row, so the 16 lanes a ds_read_b128 serves
+// hit distinct bank groups. At N = 8192, R = 1024 this is one workgroup per CU, and a quarter
+// fewer bytes per flop come from L2 than with 128 x 128 tiles (measured 28.7 against 36.4 ms per
+// 200-iteration anneal). Needs Mp % 256 == 0 and S buffers of roundup(R, 128) rows (padding rows
+// zero). Each wave loads its tile of the FP32 master state before the k loop, so that the
+// epilogue does not wait for it (27.1 -> 25.0 ms).
 // JFMT: format of J in memory and LDS, the narrowest that holds the couplings exactly (0 = BF16,
-// 1 = FP8 E4M3, 2 = FP4 E2M1), widened to BF16 in registers: the kernel is bound by streaming its
-// tiles from L2, and FP8 / FP4 rows of 64 / 32 bytes per block cut the J bytes to a half / a
-// quarter. Unit u (16 bytes) of J row q sits at u ^ f(q) with f = (q >> 1) & 7, (q >> 2) & 3,
-// (q >> 3) & 1 for the three formats, so the 16 rows one fragment read spans hit distinct banks.
+// 1 = FP8 E4M3, 2 = FP4 E2M1), widened to BF16 in registers: FP8 / FP4 rows of 64 / 32 bytes per
+// block cut the J bytes each block moves into LDS to a half / a quarter (stages of 32 / 24 KB
+// against 48; 29.3 -> 27.0 ms with FP4). Unit u (16 bytes) of J row q sits at u ^ f(q) with
+// f = (q >> 1) & 7, (q >> 2) & 3, (q >> 3) & 1 for the three formats, so the 16 rows one fragment
+// read spans hit distinct banks.
 // ------------------------------------------------------------------------------------------
 constexpr int ST_M = 256;                 // rows per workgroup
 constexpr int ST_R = 128;                 // replicas per workgroup
