@@ -860,8 +860,10 @@ size_t small_lds_bytes(int prec, int Mp, int stride) {
 // as a tiled matrix product with the fused epilogue. Workgroup (bx, by) owns rows [256 bx, +256)
 // x replicas [128 by, +128) with eight waves (two per SIMD); wave w owns rows 64 (w / 2) .. +63
 // and replicas 64 (w % 2) .. +63 (4 x 4 MFMA tiles of 16 x 16). J [Mp][Kp] and S_cur [Rp][Kp]
-// (both k contiguous) stream through a 3-stage LDS ring of 64-k blocks (256 rows of J and 128
-// replicas of S per stage) filled by direct-to-LDS loads issued two blocks ahead; unit u (8 k) of
+// (both k contiguous) stream through an LDS ring of 64-k blocks (256 rows of J and 128 replicas
+// of S per stage) filled by direct-to-LDS loads: 3 stages with one barrier per block and blocks
+// issued two ahead for BF16 J, 4 stages with one barrier per two blocks for FP8 / FP4 J (2%
+// faster; 4 stages of BF16 J do not fit in LDS); unit u (8 k) of
 // S row q sits at u ^ ((q >> 1) & 7) of its 128-byte row, so the 16 lanes a ds_read_b128 serves
 // hit distinct bank groups. At N = 8192, R = 1024 this is one workgroup per CU, and a quarter
 // fewer bytes per flop come from L2 than with 128 x 128 tiles (measured 28.7 against 36.4 ms per
@@ -888,6 +890,9 @@ struct StFmt {
   static constexpr int JB = JT / 1024;                                // 1 KB blocks of the J tile
   static constexpr int LPW = STAGE / 1024 / 8;                        // 1 KB loads per wave and block
   static constexpr int UPR = JRB / 16;                                // 16-byte units per J row
+  // blocks per barrier: two where four stages fit in LDS (FP8 / FP4 J), else one
+  static constexpr int G = JFMT == 0 ? 1 : 2;
+  static constexpr int NS = G > 1 ? 2 * G : ST_STAGES;                // stages of the LDS ring
   __device__ static __forceinline__ int swz(int q) {
     return JFMT == 0 ? ((q >> 1) & 7) : (JFMT == 1 ? ((q >> 2) & 3) : ((q >> 3) & 1));
   }
@@ -895,6 +900,9 @@ struct StFmt {
 static_assert(StFmt<0>::LPW * 8 * 1024 == StFmt<0>::STAGE && StFmt<1>::LPW * 8 * 1024 == StFmt<1>::STAGE &&
                   StFmt<2>::LPW * 8 * 1024 == StFmt<2>::STAGE,
               "every wave issues the same number of 1 KB loads per block");
+static_assert(StFmt<0>::NS * StFmt<0>::STAGE <= 160 * 1024 && StFmt<1>::NS * StFmt<1>::STAGE <= 160 * 1024 &&
+                  StFmt<2>::NS * StFmt<2>::STAGE <= 160 * 1024 && StFmt<1>::G <= 2 && StFmt<2>::G <= 2,
+              "the ring fits in LDS; the first wait of the grouped loop covers up to two blocks per group");
 
 // 8 FP8 E4M3 (two words) or 8 FP4 E2M1 values (one word; value 2b in the low nibble of byte b)
 // widened to BF16 (exact for every value of either format)
@@ -932,7 +940,7 @@ template <int JFMT>
 __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf16* __restrict__ S_cur,
                                                 __bf16* __restrict__ S_next, int t) {
   using F = StFmt<JFMT>;
-  constexpr int NS = ST_STAGES, LA = NS - 1;
+  constexpr int NS = F::NS, G = F::G;
   constexpr int LPW = F::LPW, JB = F::JB, JRB = F::JRB, UPR = F::UPR;
   extern __shared__ __align__(16) unsigned char smem_st[];  // NS x (J tile, S tile)
   const int N = a.N, Kp = a.Kp;
@@ -1027,24 +1035,11 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
       }
   }
 
-#pragma unroll
-  for (int p = 0; p < LA; ++p)
-    if (p < nkb) issue(p, p);
-  for (int kb = 0; kb < nkb; ++kb) {
-    // this wave's part of block kb has landed (the blocks after it may still be in flight)
-    const int rem = nkb - 1 - kb;
-    if (rem >= LA - 1) step_wait_vm<LPW * (LA - 1)>();
-    else if (rem == 0) step_wait_vm<0>();
-    else if (rem == 1) step_wait_vm<LPW>();
-    else step_wait_vm<2 * LPW>();
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_barrier();  // every wave's part landed; every wave is done with block kb - 1
-    __builtin_amdgcn_sched_barrier(0);
-    if (kb + LA < nkb) issue(kb + LA, (kb + LA) % NS);
-    const unsigned char* At = ring + (kb % NS) * F::STAGE + wm * JRB;
-    const unsigned char* Bt = ring + (kb % NS) * F::STAGE + F::JT + wr * 128;
-    // both k steps' fragments are read up front, so the second step's reads land under the
-    // first step's MFMAs
+  // one 64-k block: both k steps' fragments are read up front, so that the second step's reads
+  // land under the first step's MFMAs
+  auto compute = [&](int stage) {
+    const unsigned char* At = ring + stage * F::STAGE + wm * JRB;
+    const unsigned char* Bt = ring + stage * F::STAGE + F::JT + wr * 128;
     bf16x8 af[2][4], bfr[2][4];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
@@ -1063,9 +1058,62 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct)
           acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s][rt], bfr[s][ct], acc[rt][ct], 0, 0, 0);
-    // the reads of this block are complete before the next barrier frees its buffer
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  if constexpr (G > 1) {
+    // Groups of G blocks share one barrier, over a ring of 2G stages: the barrier at group kb
+    // finds blocks kb .. kb + G - 1 landed and the previous group's stages read, and the next
+    // group's blocks (issued at the previous barrier, or up front) have a whole group's work to
+    // land. Two blocks per barrier measured 2% faster than one.
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+      if (p < nkb) issue(p, p);
+    for (int kb = 0; kb < nkb; kb += G) {
+      if (kb == 0) {
+        // blocks G .. 2G - 1 of the up-front issue may still be in flight
+        const int ahead = nkb - G;
+        if (ahead >= G) step_wait_vm<LPW * G>();
+        else if (ahead == 1) step_wait_vm<LPW>();
+        else step_wait_vm<0>();
+      } else {
+        step_wait_vm<0>();
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      if (kb > 0) {
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+          if (kb + G + j < nkb) issue(kb + G + j, (kb + G + j) % NS);
+      }
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (kb + j < nkb) compute((kb + j) % NS);
+      // the reads of this group are complete before the next barrier frees its stages
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+    constexpr int LA = NS - 1;  // blocks issued ahead
+#pragma unroll
+    for (int p = 0; p < LA; ++p)
+      if (p < nkb) issue(p, p);
+    for (int kb = 0; kb < nkb; ++kb) {
+      // this wave's part of block kb has landed (the blocks after it may still be in flight)
+      const int rem = nkb - 1 - kb;
+      if (rem >= LA - 1) step_wait_vm<LPW * (LA - 1)>();
+      else if (rem == 0) step_wait_vm<0>();
+      else if (rem == 1) step_wait_vm<LPW>();
+      else step_wait_vm<2 * LPW>();
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_barrier();  // every wave's part landed; every wave is done with block kb - 1
+      __builtin_amdgcn_sched_barrier(0);
+      if (kb + LA < nkb) issue(kb + LA, (kb + LA) % NS);
+      compute(kb % NS);
+      // the reads of this block are complete before the next barrier frees its buffer
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 
   // ---- fused epilogue (the FP32 epilogue shared by every kernel) --------------------------------
@@ -1295,7 +1343,7 @@ __global__ __launch_bounds__(256, 1) void anneal_step_tiled_f64(AnnealArgs a, co
 
 template <int JFMT>
 static hipError_t launch_step_tiled(const AnnealArgs& a, const void* S_cur, void* S_next, int t, hipStream_t st) {
-  const size_t lds = (size_t)ST_STAGES * StFmt<JFMT>::STAGE;
+  const size_t lds = (size_t)StFmt<JFMT>::NS * StFmt<JFMT>::STAGE;
   hipError_t e = hipFuncSetAttribute((const void*)anneal_step_tiled<JFMT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
