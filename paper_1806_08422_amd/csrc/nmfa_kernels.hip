@@ -1068,7 +1068,8 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
 #pragma unroll
     for (int p = 0; p < NS; ++p)
       if (p < nkb) issue(p, p);
-    for (int kb = 0; kb < nkb; kb += G) {
+    int kb = 0;
+    for (; kb + G <= nkb; kb += G) {
       if (kb == 0) {
         // blocks G .. 2G - 1 of the up-front issue may still be in flight
         const int ahead = nkb - G;
@@ -1086,12 +1087,23 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
         for (int j = 0; j < G; ++j)
           if (kb + G + j < nkb) issue(kb + G + j, (kb + G + j) % NS);
       }
+      // a whole group with no branch between its blocks, so that the next block's fragment reads
+      // can be scheduled under the current block's MFMAs
 #pragma unroll
-      for (int j = 0; j < G; ++j)
-        if (kb + j < nkb) compute((kb + j) % NS);
+      for (int j = 0; j < G; ++j) compute((kb + j) % NS);
       // the reads of this group are complete before the next barrier frees its stages
       __builtin_amdgcn_s_waitcnt(0xC07F);
       __builtin_amdgcn_sched_barrier(0);
+    }
+    if (kb < nkb) {
+      // the last nkb % G blocks, issued at the previous barrier (or up front)
+      step_wait_vm<0>();
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < G - 1; ++j)
+        if (kb + j < nkb) compute((kb + j) % NS);
     }
   } else {
     constexpr int LA = NS - 1;  // blocks issued ahead
