@@ -861,15 +861,16 @@ size_t small_lds_bytes(int prec, int Mp, int stride) {
 // x replicas [128 by, +128) with eight waves (two per SIMD); wave w owns rows 64 (w / 2) .. +63
 // and replicas 64 (w % 2) .. +63 (4 x 4 MFMA tiles of 16 x 16). J [Mp][Kp] and S_cur [Rp][Kp]
 // (both k contiguous) stream through an LDS ring of 64-k blocks (256 rows of J and 128 replicas
-// of S per stage) filled by direct-to-LDS loads: 3 stages with one barrier per block and blocks
-// issued two ahead for BF16 J, 4 stages with one barrier per two blocks for FP8 / FP4 J (2%
-// faster; 4 stages of BF16 J do not fit in LDS); unit u (8 k) of
-// S row q sits at u ^ ((q >> 1) & 7) of its 128-byte row, so the 16 lanes a ds_read_b128 serves
-// hit distinct bank groups. At N = 8192, R = 1024 this is one workgroup per CU, and a quarter
-// fewer bytes per flop come from L2 than with 128 x 128 tiles (measured 28.7 against 36.4 ms per
-// 200-iteration anneal). Needs Mp % 256 == 0 and S buffers of roundup(R, 128) rows (padding rows
-// zero). Each wave loads its tile of the FP32 master state before the k loop, so that the
-// epilogue does not wait for it (27.1 -> 25.0 ms).
+// of S per stage) filled by direct-to-LDS loads: with BF16 J, 3 stages, one barrier per block and
+// blocks issued two ahead; with FP8 / FP4 J, 4 stages and one barrier per two blocks, the two
+// blocks of a group with no branch between them so that the second block's fragment reads are
+// scheduled under the first block's MFMAs (25.0 -> 23.9 ms; 4 stages of BF16 J do not fit in
+// LDS). Unit u (8 k) of S row q sits at u ^ ((q >> 1) & 7) of its 128-byte row, so the 16 lanes a
+// ds_read_b128 serves hit distinct bank groups. At N = 8192, R = 1024 this is one workgroup per
+// CU, and a quarter fewer bytes per flop come from L2 than with 128 x 128 tiles (measured 28.7
+// against 36.4 ms per 200-iteration anneal). Needs Mp % 256 == 0 and S buffers of roundup(R, 128)
+// rows (padding rows zero). Each wave loads its tile of the FP32 master state before the k loop,
+// so that the epilogue does not wait for it (27.1 -> 25.0 ms).
 // JFMT: format of J in memory and LDS, the narrowest that holds the couplings exactly (0 = BF16,
 // 1 = FP8 E4M3, 2 = FP4 E2M1), widened to BF16 in registers: FP8 / FP4 rows of 64 / 32 bytes per
 // block cut the J bytes each block moves into LDS to a half / a quarter (stages of 32 / 24 KB
