@@ -861,16 +861,17 @@ size_t small_lds_bytes(int prec, int Mp, int stride) {
 // x replicas [128 by, +128) with eight waves (two per SIMD); wave w owns rows 64 (w / 2) .. +63
 // and replicas 64 (w % 2) .. +63 (4 x 4 MFMA tiles of 16 x 16). J [Mp][Kp] and S_cur [Rp][Kp]
 // (both k contiguous) stream through an LDS ring of 64-k blocks (256 rows of J and 128 replicas
-// of S per stage) filled by direct-to-LDS loads: with BF16 J, 3 stages, one barrier per block and
-// blocks issued two ahead; with FP8 / FP4 J, 4 stages and one barrier per two blocks, the two
-// blocks of a group with no branch between them so that the second block's fragment reads are
-// scheduled under the first block's MFMAs (25.0 -> 23.9 ms; 4 stages of BF16 J do not fit in
-// LDS). Unit u (8 k) of S row q sits at u ^ ((q >> 1) & 7) of its 128-byte row, so the 16 lanes a
-// ds_read_b128 serves hit distinct bank groups. At N = 8192, R = 1024 this is one workgroup per
-// CU, and a quarter fewer bytes per flop come from L2 than with 128 x 128 tiles (measured 28.7
-// against 36.4 ms per 200-iteration anneal). Needs Mp % 256 == 0 and S buffers of roundup(R, 128)
-// rows (padding rows zero). Each wave loads its tile of the FP32 master state before the k loop,
-// so that the epilogue does not wait for it (27.1 -> 25.0 ms).
+// of S per stage) filled by direct-to-LDS loads: with BF16 J, 2 stages, one barrier per block and
+// the next block issued at each barrier (a third stage measured 3.5% slower); with FP8 / FP4 J,
+// 4 stages and one barrier per two blocks, the two blocks of a group with no branch between them
+// so that the second block's fragment reads are scheduled under the first block's MFMAs (25.0 ->
+// 23.9 ms; 4 stages of BF16 J do not fit in LDS). Unit u (8 k) of S row q sits at
+// u ^ ((q >> 1) & 7) of its 128-byte row, so the 16 lanes a ds_read_b128 serves hit distinct bank
+// groups. At N = 8192, R = 1024 this is one workgroup per CU, and a quarter fewer bytes per flop
+// come from L2 than with 128 x 128 tiles (measured 28.7 against 36.4 ms per 200-iteration
+// anneal). Needs Mp % 256 == 0 and S buffers of roundup(R, 128) rows (padding rows zero). Each
+// wave loads its tile of the FP32 master state before the k loop, so that the epilogue does not
+// wait for it (27.1 -> 25.0 ms).
 // JFMT: format of J in memory and LDS, the narrowest that holds the couplings exactly (0 = BF16,
 // 1 = FP8 E4M3, 2 = FP4 E2M1), widened to BF16 in registers: FP8 / FP4 rows of 64 / 32 bytes per
 // block cut the J bytes each block moves into LDS to a half / a quarter (stages of 32 / 24 KB
@@ -881,7 +882,7 @@ size_t small_lds_bytes(int prec, int Mp, int stride) {
 constexpr int ST_M = 256;                 // rows per workgroup
 constexpr int ST_R = 128;                 // replicas per workgroup
 constexpr int ST_K = 64;                  // k per block
-constexpr int ST_STAGES = 3;
+constexpr int ST_STAGES = 2;                // ring stages with one barrier per block (BF16 J)
 
 template <int JFMT>
 struct StFmt {
@@ -1108,6 +1109,7 @@ __device__ __forceinline__ void step_tiled_body(const AnnealArgs& a, const __bf1
     }
   } else {
     constexpr int LA = NS - 1;  // blocks issued ahead
+    static_assert(LA >= 1 && LA <= 3, "the waits below cover up to two blocks in flight");
 #pragma unroll
     for (int p = 0; p < LA; ++p)
       if (p < nkb) issue(p, p);
